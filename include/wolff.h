@@ -1,0 +1,195 @@
+/*
+ * wolff.h -- C ABI of the MI355X (gfx950) Wolff single-cluster library.
+ *
+ * The library runs the Wolff single-cluster update of the Ising model
+ * (Komura & Okabe, arXiv:1110.0899) on one GPU:
+ *   H = -J sum_<ij> S_i S_j on the periodic square (dim = 2) or simple-cubic
+ *   (dim = 3) lattice of linear size L (Section 2, Hamiltonian); each update
+ *   picks a random seed site, grows its cluster by adding parallel
+ *   neighbours with probability p = 1 - exp(-2J/T) (Section 2, steps (i)-(v);
+ *   grown frontier-parallel as in Section 4, step (iii')) and flips it.
+ *
+ * Random numbers (the paper's LCG has unstated parameters; this library fixes
+ * its own counter-based stream, so results are reproducible and independent
+ * of the traversal order):
+ *   Philox4x32-10 (Salmon et al., SC'11), key = (seed & 0xffffffff, seed >> 32)
+ *   initial spin of site i   : +1 if word 0 of philox((i, 0, 0, 2)) < 2^31, else -1
+ *   seed site of update t    : floor(((x1 << 32) | x0) * N / 2^64), x = philox((0, t, 0, 1))
+ *   bond (b, mu) in update t : word mu of philox((b, t, s, 0)), s = seed site of t;
+ *                              the bond joins b and b + e_mu and is active iff
+ *                              the word is < thr = floor(p * 2^32) (binary64).
+ *   The cluster is the connected component of s in the graph of active bonds
+ *   between sites whose spin equals s0 (the seed's spin before the update).
+ * Sites are numbered i = x + L*y (+ L*L*z), x fastest.
+ *
+ * Conventions for every call:
+ *   - Return value: WOLFF_OK (0) or a negative WOLFF_E* code; no C++
+ *     exception crosses this interface.  wolff_last_error() gives a message
+ *     for the calling thread's most recent failure.
+ *   - Host pointers are owned by the caller and only read/written during
+ *     the call.  Device memory is owned by the library.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Work is enqueued on the handle's HIP stream (its own non-blocking
+ *     stream unless wolff_set_stream was called); calls that return host
+ *     data synchronise that stream first.
+ */
+#ifndef WOLFF_H
+#define WOLFF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+#define WOLFF_OK          0
+#define WOLFF_EINVAL     -1   /* bad argument (dim, L, J, T, null pointer, size)   */
+#define WOLFF_ENOMEM     -2   /* device or host allocation failed                   */
+#define WOLFF_EDEVICE    -3   /* HIP runtime error (message in wolff_last_error)    */
+#define WOLFF_ERANGE     -4   /* update index would pass 2^32 - 2                   */
+#define WOLFF_ESTATE     -5   /* a device-side consistency check failed             */
+
+/* bond_sum value of a record taken with measurement switched off */
+#define WOLFF_NOT_MEASURED INT64_MIN
+
+/* Record of one update (Section 5, "+ measurement"): E = -J * bond_sum,
+ * bond_sum = sum_i sum_mu S_i S_{i+e_mu}; mag = sum_i S_i; csize = |C|
+ * (the paper's counter ic at the end of the update, seed included). */
+typedef struct {
+    int64_t bond_sum;
+    int64_t mag;
+    int64_t csize;
+} wolff_record;
+
+typedef struct {
+    int32_t  dim;
+    int32_t  L;
+    uint64_t n_sites;        /* N = L^dim                                      */
+    double   J;
+    double   T;
+    uint64_t seed;
+    uint32_t threshold;      /* thr = floor((1 - exp(-2J/T)) * 2^32)           */
+    int32_t  path;           /* WOLFF_PATH_* the next wolff_run will use       */
+    uint64_t t;              /* index of the next update                       */
+    int64_t  mag;            /* magnetisation after the last update            */
+    int64_t  bond_sum;       /* bond sum after the last measured update        */
+    uint64_t records_pending;/* records not yet drained by wolff_observables   */
+} wolff_info;
+
+typedef struct wolff_sim wolff_sim;
+
+/* Create a lattice of L^dim spins, iid +-1 from `seed` (update index t = 0).
+ * dim in {2, 3}; L >= 2; L^dim < 2^32; J > 0 and T > 0 finite.
+ * Allocates about 9 bytes per site of device memory (spins, the overflow
+ * queue of the one-workgroup path, the queue of the multi-workgroup path).
+ * Synchronises before returning.  *out is set only on success. */
+int wolff_create(int dim, int L, double J, double T, uint64_t seed, wolff_sim **out);
+
+/* Release the handle and its device memory (waits for its stream). NULL is ok. */
+int wolff_destroy(wolff_sim *s);
+
+/* Enqueue n_updates Wolff updates (Section 2, steps (i)-(v)); asynchronous.
+ * Appends one record per update.  WOLFF_ERANGE if t + n_updates > 2^32 - 2. */
+int wolff_run(wolff_sim *s, uint64_t n_updates);
+
+/* Wait for the stream, then move up to `cap` pending records, oldest first,
+ * into out[]; *n_out receives the number moved.  Returns WOLFF_ESTATE if a
+ * device-side consistency check (the magnetisation recount) failed. */
+int wolff_observables(wolff_sim *s, wolff_record *out, uint64_t cap, uint64_t *n_out);
+
+/* Wait for all work enqueued on the handle's stream. */
+int wolff_synchronize(wolff_sim *s);
+
+/* Current parameters and state (synchronises). */
+int wolff_get_info(wolff_sim *s, wolff_info *out);
+
+/* Copy the N spins (int8, +-1, site order) to host memory; n must equal N. */
+int wolff_get_spins(wolff_sim *s, int8_t *host, uint64_t n);
+
+/* Replace the spins (n == N, values +-1) and set the next update index to t
+ * (checkpoint resume: the state is exactly (spins, t)).  Pending records
+ * are dropped and the observables recomputed. */
+int wolff_set_spins(wolff_sim *s, const int8_t *host, uint64_t n, uint64_t t);
+
+/* 1: compute bond_sum after every update by a pass over the lattice (the
+ * paper's "+ measurement"); 0: "update only", bond_sum = WOLFF_NOT_MEASURED.
+ * mag and csize are exact in both modes.  Default 1. */
+int wolff_set_measure(wolff_sim *s, int on);
+
+/* Use the caller's HIP stream (a hipStream_t, e.g. torch's current stream)
+ * for all later work; NULL returns to the handle's own stream. */
+int wolff_set_stream(wolff_sim *s, void *hip_stream);
+
+/* Growth path: WOLFF_PATH_AUTO picks by lattice size; WOLFF_PATH_SINGLE runs
+ * every update in one workgroup (LDS frontier queue, one launch for all
+ * updates); WOLFF_PATH_TEAM runs each update on `workgroups` cooperating
+ * workgroups (0 = library default) that share an atomic-counter frontier. */
+#define WOLFF_PATH_AUTO   0
+#define WOLFF_PATH_SINGLE 1
+#define WOLFF_PATH_TEAM   2
+int wolff_set_path(wolff_sim *s, int path, int workgroups);
+
+/* Kernel timing with HIP events on the handle's stream.  While on, every
+ * launch of the cluster-growth kernel and of the measurement kernel is
+ * bracketed by events; wolff_profile_read synchronises and returns the summed
+ * milliseconds and launch counts since the last reset. */
+int wolff_profile(wolff_sim *s, int on);
+int wolff_profile_read(wolff_sim *s, double *grow_ms, uint64_t *grow_launches,
+                       double *measure_ms, uint64_t *measure_launches);
+
+/* Static description of an error code. */
+const char *wolff_strerror(int code);
+
+/* Message of the calling thread's most recent failure ("" if none). */
+const char *wolff_last_error(void);
+
+/* ------------------------------------------------------- batched replicas */
+/* Many independent lattices (any mix of dim, L, J, T, seed) advanced by one
+ * persistent launch per wolff_batch_run: each workgroup takes whole replicas
+ * from an atomic work counter, longest expected work first.  Every replica
+ * follows exactly the stream it would follow alone through wolff_sim. */
+typedef struct {
+    int32_t  dim;
+    int32_t  L;
+    double   J;
+    double   T;
+    uint64_t seed;
+    uint64_t n_updates;      /* updates this replica still has to run */
+} wolff_job;
+
+typedef struct wolff_batch wolff_batch;
+
+/* Allocate and initialise n_jobs replicas (synchronises). */
+int wolff_batch_create(const wolff_job *jobs, int n_jobs, wolff_batch **out);
+int wolff_batch_destroy(wolff_batch *b);
+
+/* Advance every replica with updates left by at most max_updates (0 = all
+ * that are left) in one launch; asynchronous. */
+int wolff_batch_run(wolff_batch *b, uint64_t max_updates);
+
+/* Pending records of replica `job` (synchronises), oldest first. */
+int wolff_batch_records(wolff_batch *b, int job, wolff_record *out, uint64_t cap,
+                        uint64_t *n_out);
+
+/* Updates still to run for replica `job`, and its next update index. */
+int wolff_batch_progress(wolff_batch *b, int job, uint64_t *left, uint64_t *t);
+
+/* Spins of replica `job` (n must equal its N; synchronises). */
+int wolff_batch_get_spins(wolff_batch *b, int job, int8_t *host, uint64_t n);
+
+int wolff_batch_set_measure(wolff_batch *b, int on);
+int wolff_batch_set_stream(wolff_batch *b, void *hip_stream);
+
+/* Workgroup size / LDS queue of the batched kernel, picked by the tuner:
+ * wg in {64, 128, 256, 512, 1024}, queue entries a power of two >= wg. */
+int wolff_batch_set_tiles(wolff_batch *b, int wg, int queue_entries);
+
+/* Elapsed milliseconds of the last wolff_batch_run's kernel (HIP events on
+ * the batch's stream; synchronises), and the number of launches it made. */
+int wolff_batch_last_ms(wolff_batch *b, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WOLFF_H */

@@ -1,0 +1,271 @@
+"""ctypes binding of libwolff (include/wolff.h): argument marshalling only.
+
+Every step of the Wolff update runs in the library's HIP kernels; this module
+only converts Python values and numpy arrays to the C ABI.  torch is imported
+first so that the library shares torch's HIP runtime in the process (and so
+that torch streams can be handed to the library); it is used for nothing
+else here.  If libwolff.so has not been built, loading fails loudly: there is
+no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+import torch  # noqa: F401  (one HIP runtime per process: torch's)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBRARY = os.path.join(HERE, "libwolff.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ERANGE, ESTATE = 0, -1, -2, -3, -4, -5
+NOT_MEASURED = -(2 ** 63)
+PATH_AUTO, PATH_SINGLE, PATH_TEAM = 0, 1, 2
+
+
+class WolffError(RuntimeError):
+    def __init__(self, code: int, where: str, message: str):
+        super().__init__("%s failed (%d): %s" % (where, code, message))
+        self.code = code
+
+
+class Record(ctypes.Structure):
+    _fields_ = [("bond_sum", ctypes.c_int64), ("mag", ctypes.c_int64), ("csize", ctypes.c_int64)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("L", ctypes.c_int32), ("n_sites", ctypes.c_uint64),
+                ("J", ctypes.c_double), ("T", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("threshold", ctypes.c_uint32), ("path", ctypes.c_int32), ("t", ctypes.c_uint64),
+                ("mag", ctypes.c_int64), ("bond_sum", ctypes.c_int64),
+                ("records_pending", ctypes.c_uint64)]
+
+
+class JobDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("L", ctypes.c_int32), ("J", ctypes.c_double),
+                ("T", ctypes.c_double), ("seed", ctypes.c_uint64), ("n_updates", ctypes.c_uint64)]
+
+
+RECORD_DTYPE = np.dtype([("bond_sum", np.int64), ("mag", np.int64), ("csize", np.int64)])
+
+# name -> (restype, argtypes); every symbol declared in include/wolff.h
+_P = ctypes.c_void_p
+_U64 = ctypes.c_uint64
+_I = ctypes.c_int
+_D = ctypes.c_double
+SIGNATURES = {
+    "wolff_create": (_I, [_I, _I, _D, _D, _U64, ctypes.POINTER(_P)]),
+    "wolff_destroy": (_I, [_P]),
+    "wolff_run": (_I, [_P, _U64]),
+    "wolff_observables": (_I, [_P, _P, _U64, ctypes.POINTER(_U64)]),
+    "wolff_synchronize": (_I, [_P]),
+    "wolff_get_info": (_I, [_P, ctypes.POINTER(Info)]),
+    "wolff_get_spins": (_I, [_P, _P, _U64]),
+    "wolff_set_spins": (_I, [_P, _P, _U64, _U64]),
+    "wolff_set_measure": (_I, [_P, _I]),
+    "wolff_set_stream": (_I, [_P, _P]),
+    "wolff_set_path": (_I, [_P, _I, _I]),
+    "wolff_profile": (_I, [_P, _I]),
+    "wolff_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_U64),
+                                ctypes.POINTER(_D), ctypes.POINTER(_U64)]),
+    "wolff_strerror": (ctypes.c_char_p, [_I]),
+    "wolff_last_error": (ctypes.c_char_p, []),
+    "wolff_batch_create": (_I, [ctypes.POINTER(JobDesc), _I, ctypes.POINTER(_P)]),
+    "wolff_batch_destroy": (_I, [_P]),
+    "wolff_batch_run": (_I, [_P, _U64]),
+    "wolff_batch_records": (_I, [_P, _I, _P, _U64, ctypes.POINTER(_U64)]),
+    "wolff_batch_progress": (_I, [_P, _I, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
+    "wolff_batch_get_spins": (_I, [_P, _I, _P, _U64]),
+    "wolff_batch_set_measure": (_I, [_P, _I]),
+    "wolff_batch_set_stream": (_I, [_P, _P]),
+    "wolff_batch_set_tiles": (_I, [_P, _I, _I]),
+    "wolff_batch_last_ms": (_I, [_P, ctypes.POINTER(_D)]),
+}
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load(path: str = LIBRARY):
+    """Load libwolff.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(path):
+                raise FileNotFoundError(
+                    "%s is missing: build it with `python -m paper_1110_0899_amd.build` "
+                    "(there is no non-HIP fallback)" % path)
+            lib = ctypes.CDLL(path)
+            for name, (res, args) in SIGNATURES.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        msg = load().wolff_last_error().decode(errors="replace")
+        raise WolffError(rc, where, msg)
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return int(stream.cuda_stream)
+    return int(stream)
+
+
+class Simulation:
+    """One lattice: wolff_create / wolff_run / wolff_observables."""
+
+    def __init__(self, dim: int, L: int, J: float, T: float, seed: int):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.wolff_create(dim, L, float(J), float(T), int(seed), ctypes.byref(h)),
+               "wolff_create")
+        self._h = h
+        self.dim, self.L, self.J, self.T, self.seed = dim, L, J, T, seed
+        self.n_sites = L ** dim
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().wolff_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def run(self, n_updates: int):
+        _check(load().wolff_run(self._h, int(n_updates)), "wolff_run")
+
+    def observables(self, cap: int | None = None) -> np.ndarray:
+        """Drain pending records: structured array (bond_sum, mag, csize)."""
+        if cap is None:
+            cap = self.info().records_pending
+        out = np.zeros(int(cap), dtype=RECORD_DTYPE)
+        n = _U64()
+        _check(load().wolff_observables(self._h, out.ctypes.data if cap else None, int(cap),
+                                        ctypes.byref(n)), "wolff_observables")
+        return out[: n.value]
+
+    def synchronize(self):
+        _check(load().wolff_synchronize(self._h), "wolff_synchronize")
+
+    def info(self) -> Info:
+        inf = Info()
+        _check(load().wolff_get_info(self._h, ctypes.byref(inf)), "wolff_get_info")
+        return inf
+
+    def spins(self) -> np.ndarray:
+        S = np.zeros(self.n_sites, dtype=np.int8)
+        _check(load().wolff_get_spins(self._h, S.ctypes.data, S.size), "wolff_get_spins")
+        return S
+
+    def set_spins(self, S: np.ndarray, t: int):
+        S = np.ascontiguousarray(S, dtype=np.int8)
+        _check(load().wolff_set_spins(self._h, S.ctypes.data, S.size, int(t)), "wolff_set_spins")
+
+    def set_measure(self, on: bool):
+        _check(load().wolff_set_measure(self._h, 1 if on else 0), "wolff_set_measure")
+
+    def set_stream(self, stream=None):
+        h = _stream_handle(stream)
+        _check(load().wolff_set_stream(self._h, h), "wolff_set_stream")
+
+    def set_path(self, path: int, workgroups: int = 0):
+        _check(load().wolff_set_path(self._h, path, workgroups), "wolff_set_path")
+
+    def profile(self, on: bool):
+        _check(load().wolff_profile(self._h, 1 if on else 0), "wolff_profile")
+
+    def profile_read(self) -> dict:
+        g, gn, m, mn = _D(), _U64(), _D(), _U64()
+        _check(load().wolff_profile_read(self._h, ctypes.byref(g), ctypes.byref(gn),
+                                         ctypes.byref(m), ctypes.byref(mn)), "wolff_profile_read")
+        return {"grow_ms": g.value, "grow_launches": gn.value,
+                "measure_ms": m.value, "measure_launches": mn.value}
+
+
+class Batch:
+    """Many replicas advanced by one persistent launch per run()."""
+
+    def __init__(self, jobs):
+        lib = load()
+        arr = (JobDesc * len(jobs))()
+        for i, j in enumerate(jobs):
+            arr[i] = JobDesc(j.dim, j.L, float(j.J), float(j.T), int(j.seed), int(j.n_updates))
+        h = ctypes.c_void_p()
+        _check(lib.wolff_batch_create(arr, len(jobs), ctypes.byref(h)), "wolff_batch_create")
+        self._h = h
+        self.jobs = list(jobs)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().wolff_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def run(self, max_updates: int = 0):
+        _check(load().wolff_batch_run(self._h, int(max_updates)), "wolff_batch_run")
+
+    def records(self, job: int) -> np.ndarray:
+        left, t = self.progress(job)
+        cap = max(int(t), 1)
+        out = np.zeros(cap, dtype=RECORD_DTYPE)
+        n = _U64()
+        _check(load().wolff_batch_records(self._h, job, out.ctypes.data, cap, ctypes.byref(n)),
+               "wolff_batch_records")
+        return out[: n.value]
+
+    def progress(self, job: int):
+        left, t = _U64(), _U64()
+        _check(load().wolff_batch_progress(self._h, job, ctypes.byref(left), ctypes.byref(t)),
+               "wolff_batch_progress")
+        return left.value, t.value
+
+    def spins(self, job: int) -> np.ndarray:
+        j = self.jobs[job]
+        S = np.zeros(j.L ** j.dim, dtype=np.int8)
+        _check(load().wolff_batch_get_spins(self._h, job, S.ctypes.data, S.size),
+               "wolff_batch_get_spins")
+        return S
+
+    def set_measure(self, on: bool):
+        _check(load().wolff_batch_set_measure(self._h, 1 if on else 0), "wolff_batch_set_measure")
+
+    def set_stream(self, stream=None):
+        _check(load().wolff_batch_set_stream(self._h, _stream_handle(stream)),
+               "wolff_batch_set_stream")
+
+    def set_tiles(self, wg: int, queue_entries: int):
+        _check(load().wolff_batch_set_tiles(self._h, wg, queue_entries), "wolff_batch_set_tiles")
+
+    def last_ms(self) -> float:
+        ms = _D()
+        _check(load().wolff_batch_last_ms(self._h, ctypes.byref(ms)), "wolff_batch_last_ms")
+        return ms.value

@@ -1,0 +1,46 @@
+"""Builds libwolff.so (HIP, gfx950) in-tree with hipcc.
+
+    python -m paper_1110_0899_amd.build
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIBRARY = os.path.join(HERE, "libwolff.so")
+SOURCES = ["wolff_lib.hip"]
+DEPENDS = ["wolff_lib.hip", "wolff_kernels.hip", "wolff_kernels.h", "wolff_device.h"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+FLAGS = [
+    "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared", "-Wall",
+    # no packed-FP32 instructions anywhere in the device code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+]
+
+
+def build(force: bool = True, verbose: bool = False) -> str:
+    """Compile the library (always when force is set)."""
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    if not force and os.path.exists(LIBRARY):
+        newest = max(os.path.getmtime(os.path.join(CSRC, d)) for d in DEPENDS)
+        newest = max(newest, os.path.getmtime(os.path.join(HERE, "..", "include", "wolff.h")))
+        if os.path.getmtime(LIBRARY) >= newest:
+            return LIBRARY
+    tmp = LIBRARY + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + ["-o", tmp] + srcs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    proc = subprocess.run(cmd, capture_output=True, text=True)
+    if proc.returncode != 0:
+        sys.stderr.write(proc.stdout + proc.stderr)
+        raise RuntimeError("hipcc failed building libwolff.so")
+    os.replace(tmp, LIBRARY)
+    return LIBRARY
+
+
+if __name__ == "__main__":
+    print(build(force=True, verbose=True))

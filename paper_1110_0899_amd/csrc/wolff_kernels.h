@@ -1,0 +1,57 @@
+// gfx950 kernels of the Wolff single-cluster update.
+//
+// Two growth paths share the per-site expansion below:
+//  * one workgroup per lattice (batch_kernel): the frontier lives in an LDS
+//    ring (spilling to a global overflow stack when it outgrows it); the
+//    workgroup runs every update of its lattice inside one launch.  Claims
+//    are workgroup-scope atomics because no other workgroup touches the
+//    lattice during the launch.  The same kernel runs one replica (the plain
+//    path for small lattices) or thousands (the batched form).
+//  * a team of workgroups per lattice (team_kernel, one launch per update):
+//    each workgroup expands from its own LDS queue and trades work through a
+//    tagged global queue with atomic head/tail counters and a pending count
+//    that decides termination; claims are agent-scope atomics.
+#pragma once
+
+#include "wolff_device.h"
+#include "../../include/wolff.h"
+
+namespace wolff {
+
+// Per-lattice descriptor in device memory, read at the start of a launch and
+// written back at its end.
+struct Rep {
+    int8_t* S;              // spins, N bytes (allocation padded to a multiple of 4)
+    uint32_t* ov;           // overflow stack of the one-workgroup path, N entries
+    wolff_record* rec;      // record array
+    uint64_t rec_count;     // records written so far
+    Geo geo;
+    int32_t dim;
+    uint32_t thr;           // floor(p * 2^32)
+    uint32_t k0, k1;        // Philox key
+    uint32_t t;             // next update index
+    uint32_t n_left;        // updates still to run
+    uint32_t measure;       // 1: bond sum after every update
+    uint32_t err;           // bit 0: magnetisation recount mismatch
+    int64_t M;              // magnetisation after the last update
+    int64_t B;              // bond sum after the last measured update
+};
+
+// Per-update control block of the team path.
+struct TeamCtl {
+    uint32_t head;          // next global queue slot to hand out
+    uint32_t tail;          // global queue slots reserved by producers
+    int32_t pending;        // sites claimed but not yet expanded, all workgroups
+    uint32_t exited;        // workgroups done with this update
+    uint32_t epoch;         // tag of this update's queue entries (never 0)
+    uint32_t s;             // seed site
+    int32_t s0;             // seed spin before the update
+    uint32_t pad;
+    unsigned long long csize;
+    long long accB;         // measurement accumulators
+    long long accM;
+    uint32_t blocks_done;
+    uint32_t pad2;
+};
+
+}  // namespace wolff

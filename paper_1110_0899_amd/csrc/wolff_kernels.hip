@@ -1,0 +1,581 @@
+// gfx950 kernels of the Wolff single-cluster update (Komura & Okabe,
+// arXiv:1110.0899, Sections 2 and 4): frontier-parallel growth of one
+// cluster per update, claim-and-flip, per-update records, and the lattice
+// reductions for the energy (Section 5, "+ measurement").
+#include "wolff_kernels.h"
+
+namespace wolff {
+
+constexpr int WAVE = 64;
+// Error bits of Rep::err.
+constexpr uint32_t ERR_MAG = 1u;          // magnetisation recount != tracked value
+constexpr uint32_t ERR_TEAM_WAIT = 2u;    // a team wait passed its bound
+// Bound on the polls of one team wait (each poll is at least ~100 ns, so the
+// bound is seconds, far above any legitimate wait).
+constexpr uint32_t TEAM_SPIN_LIMIT = 1u << 26;
+constexpr int SCOPE_WG = __HIP_MEMORY_SCOPE_WORKGROUP;
+constexpr int SCOPE_AGENT = __HIP_MEMORY_SCOPE_AGENT;
+
+// --------------------------------------------------------------- expansion
+// Step (iii') of Section 4 for one frontier site j (already in the cluster
+// and flipped): look at the 2*DIM neighbours, test the bond to each one that
+// still holds s0, and claim the neighbours whose bond is active.
+//   +mu neighbour: bond (j, mu)          -> word mu of philox((j, t, s, 0))
+//   -mu neighbour: bond (j - e_mu, mu)   -> word mu of philox((j - e_mu, t, s, 0))
+// One Philox block serves all +mu bonds of j.  Random words are only drawn
+// for eligible neighbours; the cluster does not depend on which thread
+// claims a site first, so no ordering between threads is needed.
+template <int DIM, int SCOPE>
+__device__ __forceinline__ void expand_site(bool active, uint32_t j, const Geo& g, int8_t* S,
+                                            int s0, uint32_t thr, uint32_t k0, uint32_t k1,
+                                            uint32_t t, uint32_t s, uint32_t nb[2 * DIM],
+                                            bool won[2 * DIM])
+{
+    if (!active) j = 0u;
+    neighbours<DIM>(g, j, nb);
+    bool el[2 * DIM];
+#pragma unroll
+    for (int m = 0; m < 2 * DIM; ++m) el[m] = active && (int)S[nb[m]] == s0;
+
+    uint32_t rp[3] = {0u, 0u, 0u};
+    const bool need_plus = el[0] || el[2] || (DIM == 3 && el[2 * (DIM - 1)]);
+    if (need_plus) {
+        const U4 r = philox(j, t, s, DOMAIN_BOND, k0, k1);
+        rp[0] = r.x;
+        rp[1] = r.y;
+        rp[2] = r.z;
+    }
+    bool act[2 * DIM];
+#pragma unroll
+    for (int mu = 0; mu < DIM; ++mu) {
+        act[2 * mu] = el[2 * mu] && rp[mu] < thr;
+        bool a = false;
+        if (el[2 * mu + 1]) {
+            const U4 r = philox(nb[2 * mu + 1], t, s, DOMAIN_BOND, k0, k1);
+            const uint32_t w = (mu == 0) ? r.x : (mu == 1) ? r.y : r.z;
+            a = w < thr;
+        }
+        act[2 * mu + 1] = a;
+    }
+#pragma unroll
+    for (int m = 0; m < 2 * DIM; ++m) won[m] = act[m] && claim<SCOPE>(S, nb[m], s0);
+}
+
+// Wave-level compaction of the claimed sites: one ballot per neighbour slot,
+// the lane's offset from mbcnt.  Returns the wave's item count.
+template <int DIM>
+__device__ __forceinline__ uint32_t wave_compact(const bool won[2 * DIM], uint32_t pos[2 * DIM])
+{
+    uint32_t base = 0;
+#pragma unroll
+    for (int m = 0; m < 2 * DIM; ++m) {
+        const uint64_t mask = __ballot(won[m]);
+        pos[m] = base + lane_prefix(mask);
+        base += (uint32_t)__popcll(mask);
+    }
+    return base;
+}
+
+// ------------------------------------------------------------- reductions
+// B = sum_i sum_mu S_i S_{i+e_mu} and M = sum_i S_i over one lattice by one
+// workgroup; coordinates advance incrementally (no division in the loop).
+template <int WG, int DIM>
+__device__ void reduce_lattice_wg(const int8_t* S, const Geo& g, long long* red,
+                                  int64_t& Bout, int64_t& Mout)
+{
+    constexpr int NW = WG / WAVE;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t L = g.L, N = g.N, LL = g.LL;
+    const uint32_t q0 = g.div_L(tid);
+    uint32_t x = tid - q0 * L;
+    uint32_t y = q0 - g.div_L(q0) * L;
+    const uint32_t dq = g.div_L((uint32_t)WG);
+    const uint32_t dx = (uint32_t)WG - dq * L;
+    const uint32_t dq_mod = dq - g.div_L(dq) * L;
+    int32_t b = 0, m = 0;
+    for (uint32_t i = tid; i < N; i += WG) {
+        const int si = S[i];
+        const uint32_t xp = (x + 1u == L) ? i + 1u - L : i + 1u;
+        int nsum = S[xp];
+        if (DIM == 2) {
+            const uint32_t yp = (i >= N - L) ? i - (N - L) : i + L;
+            nsum += S[yp];
+        } else {
+            const uint32_t yp = (y + 1u == L) ? i + L - LL : i + L;
+            const uint32_t zp = (i >= N - LL) ? i - (N - LL) : i + LL;
+            nsum += S[yp] + S[zp];
+        }
+        b += si * nsum;
+        m += si;
+        x += dx;
+        uint32_t carry = 0u;
+        if (x >= L) {
+            x -= L;
+            carry = 1u;
+        }
+        if (DIM == 3) {
+            y += dq_mod + carry;
+            if (y >= L) y -= L;
+        }
+    }
+    const int64_t wb = wave_sum_i64((int64_t)b);
+    const int64_t wm = wave_sum_i64((int64_t)m);
+    const uint32_t wv = tid / WAVE;
+    __syncthreads();
+    if ((tid & (WAVE - 1)) == 0) {
+        red[wv] = wb;
+        red[NW + wv] = wm;
+    }
+    __syncthreads();
+    int64_t sb = 0, sm = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        sb += red[w];
+        sm += red[NW + w];
+    }
+    Bout = sb;
+    Mout = sm;
+    __syncthreads();
+}
+
+// ------------------------------------------------- one-workgroup growth path
+// All updates of one lattice in one workgroup.  The frontier is a ring of
+// `qmask + 1` entries in LDS; when a step's new sites do not fit, they go to
+// the lattice's global overflow stack and come back when the ring runs low.
+// Items are appended in whole steps: ballot/mbcnt inside each wave, a prefix
+// over the waves' counts in LDS, one store per new site.
+template <int WG, int DIM>
+__device__ void run_rep(Rep* R, uint32_t max_updates, uint32_t qmask, uint32_t* q,
+                        uint32_t* wave_cnt, long long* red, int* sh_s0)
+{
+    constexpr int NW = WG / WAVE;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (WAVE - 1);
+    const uint32_t wv = tid / WAVE;
+
+    int8_t* S = R->S;
+    uint32_t* ov = R->ov;
+    const Geo g = R->geo;
+    const uint32_t thr = R->thr, k0 = R->k0, k1 = R->k1;
+    const uint32_t t0 = R->t;
+    uint32_t n = R->n_left;
+    if (max_updates != 0u && max_updates < n) n = max_updates;
+    wolff_record* rec = R->rec + R->rec_count;
+    int64_t M = R->M, B = R->B;
+    const bool measure = R->measure != 0u;
+    uint32_t err = 0u;
+    const uint32_t QC = qmask + 1u;
+
+    for (uint32_t u = 0; u < n; ++u) {
+        const uint32_t t = t0 + u;
+        const uint32_t s = seed_site(k0, k1, t, g.N);             // step (i)
+        if (tid == 0) {
+            const int s0 = S[s];
+            claim<SCOPE_WG>(S, s, s0);
+            q[0] = s;
+            *sh_s0 = s0;
+        }
+        __syncthreads();
+        const int s0 = *sh_s0;
+
+        uint32_t head = 0u, tail = 1u, ovn = 0u;                    // the paper's in / ic
+        uint64_t csize = 1u;
+        while (true) {
+            uint32_t avail = tail - head;
+            if (avail < (uint32_t)WG && ovn > 0u) {                 // refill the ring
+                const uint32_t m = min(ovn, QC - avail);
+                for (uint32_t i = tid; i < m; i += WG) q[(tail + i) & qmask] = ov[ovn - m + i];
+                tail += m;
+                ovn -= m;
+                __syncthreads();
+                avail = tail - head;
+            }
+            if (avail == 0u) break;                                  // step (iv) done
+            const uint32_t nproc = min(avail, (uint32_t)WG);
+            const bool active = tid < nproc;
+            const uint32_t j = active ? q[(head + tid) & qmask] : 0u;
+            head += nproc;
+
+            uint32_t nb[2 * DIM];
+            bool won[2 * DIM];
+            expand_site<DIM, SCOPE_WG>(active, j, g, S, s0, thr, k0, k1, t, s, nb, won);
+            uint32_t pos[2 * DIM];
+            const uint32_t wtot = wave_compact<DIM>(won, pos);
+            if (lane == 0) wave_cnt[wv] = wtot;
+            __syncthreads();
+            uint32_t before = 0u, total = 0u;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const uint32_t c = wave_cnt[w];
+                before += ((uint32_t)w < wv) ? c : 0u;
+                total += c;
+            }
+            if (total <= QC - (tail - head)) {
+#pragma unroll
+                for (int m = 0; m < 2 * DIM; ++m)
+                    if (won[m]) q[(tail + before + pos[m]) & qmask] = nb[m];
+                tail += total;
+            } else {
+#pragma unroll
+                for (int m = 0; m < 2 * DIM; ++m)
+                    if (won[m]) ov[ovn + before + pos[m]] = nb[m];
+                ovn += total;
+            }
+            csize += total;
+            __syncthreads();
+        }
+
+        M -= 2 * (int64_t)s0 * (int64_t)csize;                     // exact |dM| = 2|C|
+        if (measure) {
+            int64_t Bm, Mm;
+            reduce_lattice_wg<WG, DIM>(S, g, red, Bm, Mm);
+            B = Bm;
+            if (Mm != M) err |= ERR_MAG;
+        }
+        if (tid == 0) {
+            wolff_record r;
+            r.bond_sum = measure ? B : (int64_t)WOLFF_NOT_MEASURED;
+            r.mag = M;
+            r.csize = (int64_t)csize;
+            rec[u] = r;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        R->t = t0 + n;
+        R->n_left -= n;
+        R->rec_count += n;
+        R->M = M;
+        R->B = B;
+        R->err |= err;
+    }
+}
+
+template <int WG>
+__global__ __launch_bounds__(WG) void batch_kernel(Rep* reps, const uint32_t* order,
+                                                   uint32_t n_reps, uint32_t* next,
+                                                   uint32_t max_updates, uint32_t qmask)
+{
+    extern __shared__ uint32_t q[];
+    __shared__ uint32_t wave_cnt[WG / WAVE];
+    __shared__ long long red[2 * (WG / WAVE)];
+    __shared__ int sh_s0;
+    __shared__ uint32_t sh_idx;
+    uint32_t idx = blockIdx.x;
+    while (idx < n_reps) {
+        Rep* R = reps + order[idx];
+        if (R->dim == 2)
+            run_rep<WG, 2>(R, max_updates, qmask, q, wave_cnt, red, &sh_s0);
+        else
+            run_rep<WG, 3>(R, max_updates, qmask, q, wave_cnt, red, &sh_s0);
+        if (threadIdx.x == 0) sh_idx = gridDim.x + atomicAdd(next, 1u);
+        __syncthreads();
+        idx = sh_idx;
+        __syncthreads();
+    }
+}
+
+__global__ void reset_counter_kernel(uint32_t* c)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0u;
+}
+
+// Initial state: iid +-1 from the domain-2 stream.
+__global__ void init_kernel(int8_t* S, uint32_t N, uint32_t k0, uint32_t k1)
+{
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+        const U4 r = philox(i, 0u, 0u, DOMAIN_INIT, k0, k1);
+        S[i] = (r.x < 0x80000000u) ? (int8_t)1 : (int8_t)-1;
+    }
+}
+
+// (B, M) of one lattice by one workgroup, written to its descriptor.
+template <int WG>
+__global__ __launch_bounds__(WG) void measure_rep_kernel(Rep* R)
+{
+    __shared__ long long red[2 * (WG / WAVE)];
+    int64_t B, M;
+    const Geo g = R->geo;
+    if (R->dim == 2)
+        reduce_lattice_wg<WG, 2>(R->S, g, red, B, M);
+    else
+        reduce_lattice_wg<WG, 3>(R->S, g, red, B, M);
+    if (threadIdx.x == 0) {
+        R->B = B;
+        R->M = M;
+    }
+}
+
+// ------------------------------------------------ multi-workgroup team path
+// One update of one lattice by a team of workgroups.  team_seed_kernel draws
+// the seed site, claims it and publishes it as entry 0 of the global queue.
+// Every team workgroup expands sites from its own LDS ring; new sites beyond
+// `keep` go to the global queue (slots reserved with one atomicAdd on tail,
+// each entry tagged with the update's epoch so that a reader can tell a
+// written slot from a reserved one); a workgroup whose ring is empty takes a
+// chunk of slots with a CAS on head.  pending counts claimed sites not yet
+// expanded: a workgroup adds (new - expanded) once per step, before its new
+// sites become visible, so pending reaches 0 exactly when the cluster is
+// complete (steps (iii)-(iv) of Section 2).  The last workgroup to leave
+// writes the magnetisation and, without measurement, the record.
+__global__ void team_seed_kernel(Rep* R, TeamCtl* ctl, unsigned long long* gq)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const Geo g = R->geo;
+    const uint32_t t = R->t;
+    const uint32_t s = seed_site(R->k0, R->k1, t, g.N);
+    int8_t* S = R->S;
+    const int s0 = S[s];
+    claim<SCOPE_AGENT>(S, s, s0);
+    uint32_t epoch = ctl->epoch + 1u;
+    if (epoch == 0u) epoch = 1u;
+    ctl->epoch = epoch;
+    ctl->s = s;
+    ctl->s0 = s0;
+    ctl->head = 0u;
+    ctl->tail = 1u;
+    ctl->pending = 1;
+    ctl->exited = 0u;
+    ctl->csize = 1ull;
+    ctl->accB = 0;
+    ctl->accM = 0;
+    ctl->blocks_done = 0u;
+    gq[0] = ((unsigned long long)epoch << 32) | s;
+}
+
+template <int WG, int DIM>
+__global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned long long* gq,
+                                                  uint32_t qmask, uint32_t keep)
+{
+    constexpr int NW = WG / WAVE;
+    extern __shared__ uint32_t q[];
+    __shared__ uint32_t wave_cnt[NW];
+    __shared__ uint32_t sh_take[3];   // first slot, count, done flag
+    __shared__ uint32_t sh_push;
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (WAVE - 1);
+    const uint32_t wv = tid / WAVE;
+    int8_t* S = R->S;
+    const Geo g = R->geo;
+    const uint32_t thr = R->thr, k0 = R->k0, k1 = R->k1, t = R->t;
+    const uint32_t s = ctl->s;
+    const int s0 = ctl->s0;
+    const uint32_t epoch = ctl->epoch;
+
+    uint32_t head = 0u, tail = 0u;           // local ring
+    uint64_t my_claims = 0u;
+    while (true) {
+        if (tail == head) {
+            // take a chunk from the global queue, or leave when pending is 0
+            if (tid == 0) {
+                uint32_t first = 0u, cnt = 0u, done = 0u;
+                uint32_t backoff = 1u, polls = 0u;
+                while (true) {
+                    if (++polls > TEAM_SPIN_LIMIT) {           // never expected: flag and leave
+                        __hip_atomic_fetch_or(&R->err, ERR_TEAM_WAIT, __ATOMIC_RELAXED, SCOPE_AGENT);
+                        done = 1u;
+                        break;
+                    }
+                    const uint32_t h = __hip_atomic_load(&ctl->head, __ATOMIC_RELAXED, SCOPE_AGENT);
+                    const uint32_t tl = __hip_atomic_load(&ctl->tail, __ATOMIC_RELAXED, SCOPE_AGENT);
+                    if (h < tl) {
+                        uint32_t want = tl - h;
+                        if (want > (uint32_t)WG) want = WG;
+                        uint32_t expected = h;
+                        if (__hip_atomic_compare_exchange_strong(&ctl->head, &expected, h + want,
+                                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                                 SCOPE_AGENT)) {
+                            first = h;
+                            cnt = want;
+                            break;
+                        }
+                        continue;
+                    }
+                    if (__hip_atomic_load(&ctl->pending, __ATOMIC_RELAXED, SCOPE_AGENT) == 0) {
+                        done = 1u;
+                        break;
+                    }
+                    // back off: up to 8 x 64 cycles between polls
+                    for (uint32_t b = 0; b < backoff; ++b) __builtin_amdgcn_s_sleep(1);
+                    if (backoff < 8u) backoff <<= 1;
+                }
+                sh_take[0] = first;
+                sh_take[1] = cnt;
+                sh_take[2] = done;
+            }
+            __syncthreads();
+            const uint32_t first = sh_take[0], cnt = sh_take[1], done = sh_take[2];
+            __syncthreads();
+            if (done) break;
+            if (tid < cnt) {
+                // the slot was reserved by a running producer that writes it
+                // right after its reservation; the wait is bounded anyway
+                unsigned long long v = __hip_atomic_load(&gq[first + tid], __ATOMIC_RELAXED, SCOPE_AGENT);
+                uint32_t polls = 0u;
+                while ((uint32_t)(v >> 32) != epoch) {
+                    if (++polls > TEAM_SPIN_LIMIT) {
+                        __hip_atomic_fetch_or(&R->err, ERR_TEAM_WAIT, __ATOMIC_RELAXED, SCOPE_AGENT);
+                        v = ((unsigned long long)epoch << 32) | s;   // a member already: expands to nothing
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    v = __hip_atomic_load(&gq[first + tid], __ATOMIC_RELAXED, SCOPE_AGENT);
+                }
+                q[(tail + tid) & qmask] = (uint32_t)v;
+            }
+            tail += cnt;
+            __syncthreads();
+        }
+
+        const uint32_t avail = tail - head;
+        const uint32_t nproc = min(avail, (uint32_t)WG);
+        const bool active = tid < nproc;
+        const uint32_t j = active ? q[(head + tid) & qmask] : 0u;
+        head += nproc;
+
+        uint32_t nb[2 * DIM];
+        bool won[2 * DIM];
+        expand_site<DIM, SCOPE_AGENT>(active, j, g, S, s0, thr, k0, k1, t, s, nb, won);
+        uint32_t pos[2 * DIM];
+        const uint32_t wtot = wave_compact<DIM>(won, pos);
+        if (lane == 0) wave_cnt[wv] = wtot;
+        __syncthreads();
+        uint32_t before = 0u, total = 0u;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t c = wave_cnt[w];
+            before += ((uint32_t)w < wv) ? c : 0u;
+            total += c;
+        }
+        // keep up to `keep` sites locally, publish the rest
+        const uint32_t local_now = tail - head;
+        uint32_t n_keep = 0u;
+        if (local_now < keep) n_keep = min(total, keep - local_now);
+        const uint32_t n_push = total - n_keep;
+        if (tid == 0) {
+            const int32_t delta = (int32_t)total - (int32_t)nproc;
+            if (delta != 0) __hip_atomic_fetch_add(&ctl->pending, delta, __ATOMIC_RELAXED, SCOPE_AGENT);
+            if (n_push > 0u)
+                sh_push = __hip_atomic_fetch_add(&ctl->tail, n_push, __ATOMIC_RELAXED, SCOPE_AGENT);
+        }
+        __syncthreads();
+        const uint32_t gbase = sh_push;
+#pragma unroll
+        for (int m = 0; m < 2 * DIM; ++m) {
+            if (won[m]) {
+                const uint32_t r = before + pos[m];
+                if (r < n_keep) {
+                    q[(tail + r) & qmask] = nb[m];
+                } else {
+                    const unsigned long long v = ((unsigned long long)epoch << 32) | nb[m];
+                    __hip_atomic_store(&gq[gbase + (r - n_keep)], v, __ATOMIC_RELAXED, SCOPE_AGENT);
+                }
+            }
+        }
+        tail += n_keep;
+        my_claims += total;
+        __syncthreads();
+    }
+
+    if (tid == 0) {
+        if (my_claims)
+            __hip_atomic_fetch_add(&ctl->csize, (unsigned long long)my_claims, __ATOMIC_RELAXED,
+                                   SCOPE_AGENT);
+        const uint32_t prev =
+            __hip_atomic_fetch_add(&ctl->exited, 1u, __ATOMIC_ACQ_REL, SCOPE_AGENT);
+        if (prev == gridDim.x - 1u) {
+            const unsigned long long csize =
+                __hip_atomic_load(&ctl->csize, __ATOMIC_RELAXED, SCOPE_AGENT);
+            const int64_t M = R->M - 2 * (int64_t)s0 * (int64_t)csize;
+            R->M = M;
+            if (R->measure == 0u) {
+                wolff_record r;
+                r.bond_sum = (int64_t)WOLFF_NOT_MEASURED;
+                r.mag = M;
+                r.csize = (int64_t)csize;
+                R->rec[R->rec_count] = r;
+                R->rec_count += 1u;
+                R->t = t + 1u;
+            }
+        }
+    }
+}
+
+// Grid-wide (B, M) after a team update; the last block writes the record.
+template <int DIM>
+__global__ __launch_bounds__(256) void measure_grid_kernel(Rep* R, TeamCtl* ctl)
+{
+    constexpr int WG = 256, NW = WG / WAVE;
+    __shared__ long long red[2 * NW];
+    const Geo g = R->geo;
+    const int8_t* S = R->S;
+    const uint32_t L = g.L, N = g.N, LL = g.LL;
+    int32_t b = 0, m = 0;
+    const uint32_t stride = gridDim.x * WG;
+    for (uint32_t i = blockIdx.x * WG + threadIdx.x; i < N; i += stride) {
+        const uint32_t q = g.div_L(i);
+        const uint32_t x = i - q * L;
+        const int si = S[i];
+        const uint32_t xp = (x + 1u == L) ? i + 1u - L : i + 1u;
+        int nsum = S[xp];
+        if (DIM == 2) {
+            const uint32_t yp = (i >= N - L) ? i - (N - L) : i + L;
+            nsum += S[yp];
+        } else {
+            const uint32_t y = q - g.div_L(q) * L;
+            const uint32_t yp = (y + 1u == L) ? i + L - LL : i + L;
+            const uint32_t zp = (i >= N - LL) ? i - (N - LL) : i + LL;
+            nsum += S[yp] + S[zp];
+        }
+        b += si * nsum;
+        m += si;
+    }
+    const int64_t wb = wave_sum_i64((int64_t)b);
+    const int64_t wm = wave_sum_i64((int64_t)m);
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        red[threadIdx.x / WAVE] = wb;
+        red[NW + threadIdx.x / WAVE] = wm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t sb = 0, sm = 0;
+        for (int w = 0; w < NW; ++w) {
+            sb += red[w];
+            sm += red[NW + w];
+        }
+        __hip_atomic_fetch_add(&ctl->accB, (long long)sb, __ATOMIC_RELAXED, SCOPE_AGENT);
+        __hip_atomic_fetch_add(&ctl->accM, (long long)sm, __ATOMIC_RELAXED, SCOPE_AGENT);
+        const uint32_t prev =
+            __hip_atomic_fetch_add(&ctl->blocks_done, 1u, __ATOMIC_ACQ_REL, SCOPE_AGENT);
+        if (prev == gridDim.x - 1u) {
+            const int64_t B = __hip_atomic_load(&ctl->accB, __ATOMIC_RELAXED, SCOPE_AGENT);
+            const int64_t Mm = __hip_atomic_load(&ctl->accM, __ATOMIC_RELAXED, SCOPE_AGENT);
+            const int64_t M = R->M;
+            if (Mm != M) R->err |= ERR_MAG;
+            R->B = B;
+            wolff_record r;
+            r.bond_sum = B;
+            r.mag = M;
+            r.csize = (int64_t)ctl->csize;
+            R->rec[R->rec_count] = r;
+            R->rec_count += 1u;
+            R->t = R->t + 1u;
+        }
+    }
+}
+
+// explicit instantiations used by the host code
+template __global__ void batch_kernel<64>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t);
+template __global__ void batch_kernel<128>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t);
+template __global__ void batch_kernel<256>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t);
+template __global__ void batch_kernel<512>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t);
+template __global__ void batch_kernel<1024>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t);
+template __global__ void measure_rep_kernel<1024>(Rep*);
+template __global__ void team_kernel<256, 2>(Rep*, TeamCtl*, unsigned long long*, uint32_t, uint32_t);
+template __global__ void team_kernel<256, 3>(Rep*, TeamCtl*, unsigned long long*, uint32_t, uint32_t);
+template __global__ void measure_grid_kernel<2>(Rep*, TeamCtl*);
+template __global__ void measure_grid_kernel<3>(Rep*, TeamCtl*);
+
+}  // namespace wolff

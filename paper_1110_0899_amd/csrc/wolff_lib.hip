@@ -1,0 +1,876 @@
+// Host runtime and C ABI of libwolff (declared in include/wolff.h).
+// One translation unit: the kernels are included so that the launch sites
+// below see their definitions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "wolff_kernels.hip"
+
+using wolff::Geo;
+using wolff::Rep;
+using wolff::TeamCtl;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+static int fail(int code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            return fail(e_ == hipErrorOutOfMemory ? WOLFF_ENOMEM : WOLFF_EDEVICE,       \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));             \
+        }                                                                               \
+    } while (0)
+
+extern "C" const char* wolff_strerror(int code)
+{
+    switch (code) {
+    case WOLFF_OK: return "ok";
+    case WOLFF_EINVAL: return "invalid argument";
+    case WOLFF_ENOMEM: return "out of memory";
+    case WOLFF_EDEVICE: return "HIP runtime error";
+    case WOLFF_ERANGE: return "update index out of range";
+    case WOLFF_ESTATE: return "device consistency check failed";
+    default: return "unknown error";
+    }
+}
+
+extern "C" const char* wolff_last_error(void) { return g_last_error.c_str(); }
+
+static std::string err_message(uint32_t bits)
+{
+    std::string m;
+    if (bits & wolff::ERR_MAG) m += "magnetisation recount disagrees with the cluster sizes; ";
+    if (bits & wolff::ERR_TEAM_WAIT) m += "a multi-workgroup wait passed its bound; ";
+    if (m.empty()) m = "device error flag set";
+    return m;
+}
+
+// -------------------------------------------------------------- parameters
+// thr = floor(p * 2^32), p = 1 - exp(-2J/T) (Section 2, step (ii)), binary64.
+static uint32_t bond_threshold(double J, double T)
+{
+    const double p = 1.0 - std::exp(-2.0 * J / T);
+    const double scaled = std::ldexp(p, 32);
+    if (!(scaled > 0.0)) return 0u;
+    if (scaled >= 4294967295.0) return 0xFFFFFFFFu;
+    return (uint32_t)std::floor(scaled);
+}
+
+static Geo make_geo(int dim, uint32_t L)
+{
+    Geo g;
+    g.L = L;
+    g.LL = L * L;
+    g.N = (dim == 2) ? g.LL : g.LL * L;
+    if ((L & (L - 1u)) == 0u) {
+        uint32_t sh = 0;
+        while ((1u << sh) < L) ++sh;
+        g.shift = sh;
+        g.magic_hi = g.magic_lo = 0u;
+    } else {
+        g.shift = 0xFFFFFFFFu;
+        const uint64_t M = UINT64_MAX / L + 1u;     // floor(2^64 / L) + 1
+        g.magic_hi = (uint32_t)(M >> 32);
+        g.magic_lo = (uint32_t)M;
+    }
+    return g;
+}
+
+static int check_params(int dim, int L, double J, double T, uint64_t* N)
+{
+    if (dim != 2 && dim != 3) return fail(WOLFF_EINVAL, "dim must be 2 or 3");
+    if (L < 2) return fail(WOLFF_EINVAL, "L must be >= 2");
+    if (!(std::isfinite(J) && J > 0.0)) return fail(WOLFF_EINVAL, "J must be finite and > 0");
+    if (!(std::isfinite(T) && T > 0.0)) return fail(WOLFF_EINVAL, "T must be finite and > 0");
+    uint64_t n = 1;
+    for (int a = 0; a < dim; ++a) {
+        n *= (uint64_t)L;
+        if (n >= (1ull << 32)) return fail(WOLFF_EINVAL, "L^dim must be < 2^32");
+    }
+    *N = n;
+    return WOLFF_OK;
+}
+
+static constexpr uint64_t T_LIMIT = 0xFFFFFFFEull;   // t + 1 must fit the 32-bit counter word
+
+static uint64_t padded_bytes(uint64_t N) { return (N + 255u) & ~uint64_t(255); }
+
+// -------------------------------------------------------- kernel dispatch
+static int g_num_cus = 0;
+
+static int device_cus()
+{
+    if (g_num_cus == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            g_num_cus = prop.multiProcessorCount;
+        if (g_num_cus <= 0) g_num_cus = 256;
+    }
+    return g_num_cus;
+}
+
+static hipError_t launch_batch(int wg, uint32_t grid, uint32_t qentries, hipStream_t st, Rep* reps,
+                               const uint32_t* order, uint32_t n, uint32_t* next, uint32_t max_updates)
+{
+    const size_t lds = (size_t)qentries * sizeof(uint32_t);
+    const uint32_t qmask = qentries - 1u;
+    hipLaunchKernelGGL(wolff::reset_counter_kernel, dim3(1), dim3(64), 0, st, next);
+    switch (wg) {
+    case 64:
+        hipLaunchKernelGGL(wolff::batch_kernel<64>, dim3(grid), dim3(64), lds, st, reps, order, n, next, max_updates, qmask);
+        break;
+    case 128:
+        hipLaunchKernelGGL(wolff::batch_kernel<128>, dim3(grid), dim3(128), lds, st, reps, order, n, next, max_updates, qmask);
+        break;
+    case 512:
+        hipLaunchKernelGGL(wolff::batch_kernel<512>, dim3(grid), dim3(512), lds, st, reps, order, n, next, max_updates, qmask);
+        break;
+    case 1024:
+        hipLaunchKernelGGL(wolff::batch_kernel<1024>, dim3(grid), dim3(1024), lds, st, reps, order, n, next, max_updates, qmask);
+        break;
+    default:
+        hipLaunchKernelGGL(wolff::batch_kernel<256>, dim3(grid), dim3(256), lds, st, reps, order, n, next, max_updates, qmask);
+        break;
+    }
+    return hipGetLastError();
+}
+
+static bool valid_tiles(int wg, int q)
+{
+    if (wg != 64 && wg != 128 && wg != 256 && wg != 512 && wg != 1024) return false;
+    if (q < wg || q > 16384 || (q & (q - 1)) != 0) return false;
+    return true;
+}
+
+// ====================================================================== sim
+struct EventPair {
+    hipEvent_t a, b;
+};
+
+struct wolff_sim {
+    int dim = 2;
+    int L = 0;
+    uint64_t N = 0;
+    double J = 1.0, T = 1.0;
+    uint64_t seed = 0;
+    uint32_t thr = 0;
+    Geo geo{};
+
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+
+    int8_t* S = nullptr;
+    uint32_t* ov = nullptr;
+    unsigned long long* gq = nullptr;
+    Rep* d_rep = nullptr;
+    uint32_t* d_order = nullptr;
+    uint32_t* d_next = nullptr;
+    TeamCtl* d_ctl = nullptr;
+    wolff_record* d_rec = nullptr;
+    uint64_t rec_cap = 0;
+    uint64_t rec_written = 0;    // records the device has been asked to write
+    uint64_t rec_read = 0;
+
+    uint64_t t = 0;
+    int measure = 1;
+    int path = WOLFF_PATH_AUTO;
+    int team_wgs = 0;
+    int single_wg = 256;
+    int single_q = 2048;
+
+    bool profiling = false;
+    std::vector<EventPair> ev_grow, ev_meas, ev_free;
+    double grow_ms = 0.0, meas_ms = 0.0;
+    uint64_t grow_n = 0, meas_n = 0;
+};
+
+static int resolved_path(const wolff_sim* s)
+{
+    if (s->path != WOLFF_PATH_AUTO) return s->path;
+    return (s->N >= (1ull << 20)) ? WOLFF_PATH_TEAM : WOLFF_PATH_SINGLE;
+}
+
+static int team_size(const wolff_sim* s)
+{
+    if (s->team_wgs > 0) return s->team_wgs;
+    return std::max(8, device_cus() / 4);
+}
+
+static void free_sim(wolff_sim* s)
+{
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (auto* v : {&s->ev_grow, &s->ev_meas, &s->ev_free})
+        for (auto& e : *v) {
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
+        }
+    if (s->S) (void)hipFree(s->S);
+    if (s->ov) (void)hipFree(s->ov);
+    if (s->gq) (void)hipFree(s->gq);
+    if (s->d_rep) (void)hipFree(s->d_rep);
+    if (s->d_order) (void)hipFree(s->d_order);
+    if (s->d_next) (void)hipFree(s->d_next);
+    if (s->d_ctl) (void)hipFree(s->d_ctl);
+    if (s->d_rec) (void)hipFree(s->d_rec);
+    if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
+    delete s;
+}
+
+static int get_event_pair(wolff_sim* s, EventPair* out)
+{
+    if (!s->ev_free.empty()) {
+        *out = s->ev_free.back();
+        s->ev_free.pop_back();
+        return WOLFF_OK;
+    }
+    HIP_TRY(hipEventCreate(&out->a));
+    HIP_TRY(hipEventCreate(&out->b));
+    return WOLFF_OK;
+}
+
+static int harvest_events(wolff_sim* s)
+{
+    for (int which = 0; which < 2; ++which) {
+        auto& v = which == 0 ? s->ev_grow : s->ev_meas;
+        for (auto& e : v) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventSynchronize(e.b));
+            HIP_TRY(hipEventElapsedTime(&ms, e.a, e.b));
+            if (which == 0) {
+                s->grow_ms += ms;
+                s->grow_n += 1;
+            } else {
+                s->meas_ms += ms;
+                s->meas_n += 1;
+            }
+            s->ev_free.push_back(e);
+        }
+        v.clear();
+    }
+    return WOLFF_OK;
+}
+
+// Copy the host-side fields of the descriptor (stream must be idle).
+static int push_rep(wolff_sim* s, const Rep& r)
+{
+    HIP_TRY(hipMemcpy(s->d_rep, &r, sizeof(Rep), hipMemcpyHostToDevice));
+    return WOLFF_OK;
+}
+
+static int pull_rep(wolff_sim* s, Rep* r)
+{
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(hipMemcpy(r, s->d_rep, sizeof(Rep), hipMemcpyDeviceToHost));
+    return WOLFF_OK;
+}
+
+static int measure_now(wolff_sim* s)
+{
+    hipLaunchKernelGGL(wolff::measure_rep_kernel<1024>, dim3(1), dim3(1024), 0, s->stream, s->d_rep);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_create(int dim, int L, double J, double T, uint64_t seed, wolff_sim** out)
+{
+    if (!out) return fail(WOLFF_EINVAL, "out is NULL");
+    uint64_t N = 0;
+    int rc = check_params(dim, L, J, T, &N);
+    if (rc) return rc;
+    wolff_sim* s = new (std::nothrow) wolff_sim();
+    if (!s) return fail(WOLFF_ENOMEM, "host allocation failed");
+    s->dim = dim;
+    s->L = L;
+    s->N = N;
+    s->J = J;
+    s->T = T;
+    s->seed = seed;
+    s->thr = bond_threshold(J, T);
+    s->geo = make_geo(dim, (uint32_t)L);
+
+#define CREATE_TRY(expr)                                                                \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            int code_ = e_ == hipErrorOutOfMemory ? WOLFF_ENOMEM : WOLFF_EDEVICE;       \
+            free_sim(s);                                                                \
+            return fail(code_, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+        }                                                                               \
+    } while (0)
+
+    CREATE_TRY(hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking));
+    s->stream = s->own_stream;
+    CREATE_TRY(hipMalloc(&s->S, padded_bytes(N)));
+    CREATE_TRY(hipMemset(s->S, 0, padded_bytes(N)));
+    CREATE_TRY(hipMalloc(&s->ov, N * sizeof(uint32_t)));
+    CREATE_TRY(hipMalloc(&s->d_rep, sizeof(Rep)));
+    CREATE_TRY(hipMalloc(&s->d_order, sizeof(uint32_t)));
+    CREATE_TRY(hipMalloc(&s->d_next, sizeof(uint32_t)));
+    CREATE_TRY(hipMalloc(&s->d_ctl, sizeof(TeamCtl)));
+    CREATE_TRY(hipMemset(s->d_ctl, 0, sizeof(TeamCtl)));
+    CREATE_TRY(hipMemset(s->d_order, 0, sizeof(uint32_t)));
+    s->rec_cap = 1024;
+    CREATE_TRY(hipMalloc(&s->d_rec, s->rec_cap * sizeof(wolff_record)));
+
+    hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((N + 255) / 256, 65536)),
+                       dim3(256), 0, s->stream, s->S, (uint32_t)N, (uint32_t)seed,
+                       (uint32_t)(seed >> 32));
+    CREATE_TRY(hipGetLastError());
+
+    Rep r{};
+    r.S = s->S;
+    r.ov = s->ov;
+    r.rec = s->d_rec;
+    r.rec_count = 0;
+    r.geo = s->geo;
+    r.dim = dim;
+    r.thr = s->thr;
+    r.k0 = (uint32_t)seed;
+    r.k1 = (uint32_t)(seed >> 32);
+    r.t = 0;
+    r.n_left = 0xFFFFFFFFu;
+    r.measure = 1;
+    r.err = 0;
+    CREATE_TRY(hipStreamSynchronize(s->stream));
+    CREATE_TRY(hipMemcpy(s->d_rep, &r, sizeof(Rep), hipMemcpyHostToDevice));
+    if ((rc = measure_now(s)) != WOLFF_OK) {
+        free_sim(s);
+        return rc;
+    }
+#undef CREATE_TRY
+    *out = s;
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_destroy(wolff_sim* s)
+{
+    free_sim(s);
+    return WOLFF_OK;
+}
+
+// Make room for n more records on the device (synchronises if it grows).
+static int reserve_records(wolff_sim* s, uint64_t n)
+{
+    const uint64_t need = s->rec_written + n;
+    if (need <= s->rec_cap) return WOLFF_OK;
+    uint64_t cap = s->rec_cap;
+    while (cap < need) cap *= 2;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    wolff_record* nrec = nullptr;
+    HIP_TRY(hipMalloc(&nrec, cap * sizeof(wolff_record)));
+    const uint64_t live = s->rec_written - s->rec_read;
+    if (live)
+        HIP_TRY(hipMemcpy(nrec, s->d_rec + s->rec_read, live * sizeof(wolff_record),
+                          hipMemcpyDeviceToDevice));
+    HIP_TRY(hipFree(s->d_rec));
+    s->d_rec = nrec;
+    s->rec_cap = cap;
+    s->rec_written = live;
+    s->rec_read = 0;
+    Rep r;
+    int rc = pull_rep(s, &r);
+    if (rc) return rc;
+    r.rec = nrec;
+    r.rec_count = live;
+    return push_rep(s, r);
+}
+
+static int ensure_team_queue(wolff_sim* s)
+{
+    if (s->gq) return WOLFF_OK;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(hipMalloc(&s->gq, s->N * sizeof(unsigned long long)));
+    HIP_TRY(hipMemset(s->gq, 0, s->N * sizeof(unsigned long long)));
+    return WOLFF_OK;
+}
+
+static int run_team_update(wolff_sim* s)
+{
+    const int G = team_size(s);
+    constexpr int WG = 256;
+    const uint32_t qentries = 2048;
+    const uint32_t keep = 2 * WG;
+    EventPair ev{};
+    hipLaunchKernelGGL(wolff::team_seed_kernel, dim3(1), dim3(64), 0, s->stream, s->d_rep, s->d_ctl, s->gq);
+    if (s->profiling) {
+        int rc = get_event_pair(s, &ev);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(ev.a, s->stream));
+    }
+    if (s->dim == 2)
+        hipLaunchKernelGGL((wolff::team_kernel<WG, 2>), dim3(G), dim3(WG), qentries * sizeof(uint32_t),
+                           s->stream, s->d_rep, s->d_ctl, s->gq, qentries - 1u, keep);
+    else
+        hipLaunchKernelGGL((wolff::team_kernel<WG, 3>), dim3(G), dim3(WG), qentries * sizeof(uint32_t),
+                           s->stream, s->d_rep, s->d_ctl, s->gq, qentries - 1u, keep);
+    HIP_TRY(hipGetLastError());
+    if (s->profiling) {
+        HIP_TRY(hipEventRecord(ev.b, s->stream));
+        s->ev_grow.push_back(ev);
+    }
+    if (s->measure) {
+        EventPair em{};
+        if (s->profiling) {
+            int rc = get_event_pair(s, &em);
+            if (rc) return rc;
+            HIP_TRY(hipEventRecord(em.a, s->stream));
+        }
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>((s->N + 255) / 256, 4096);
+        if (s->dim == 2)
+            hipLaunchKernelGGL(wolff::measure_grid_kernel<2>, dim3(blocks), dim3(256), 0, s->stream, s->d_rep, s->d_ctl);
+        else
+            hipLaunchKernelGGL(wolff::measure_grid_kernel<3>, dim3(blocks), dim3(256), 0, s->stream, s->d_rep, s->d_ctl);
+        HIP_TRY(hipGetLastError());
+        if (s->profiling) {
+            HIP_TRY(hipEventRecord(em.b, s->stream));
+            s->ev_meas.push_back(em);
+        }
+    }
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_run(wolff_sim* s, uint64_t n)
+{
+    if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
+    if (n == 0) return WOLFF_OK;
+    if (s->t + n > T_LIMIT) return fail(WOLFF_ERANGE, "t + n_updates exceeds 2^32 - 2");
+    int rc = reserve_records(s, n);
+    if (rc) return rc;
+    const int path = resolved_path(s);
+    if (path == WOLFF_PATH_TEAM) {
+        if ((rc = ensure_team_queue(s))) return rc;
+        for (uint64_t u = 0; u < n; ++u)
+            if ((rc = run_team_update(s))) return rc;
+    } else {
+        // one workgroup runs the updates; chunk so that one launch stays short
+        const uint64_t chunk = std::max<uint64_t>(1, (1ull << 26) / std::max<uint64_t>(s->N, 1));
+        for (uint64_t done = 0; done < n;) {
+            const uint32_t m = (uint32_t)std::min<uint64_t>(chunk, n - done);
+            EventPair ev{};
+            if (s->profiling) {
+                if ((rc = get_event_pair(s, &ev))) return rc;
+                HIP_TRY(hipEventRecord(ev.a, s->stream));
+            }
+            HIP_TRY(launch_batch(s->single_wg, 1, (uint32_t)s->single_q, s->stream, s->d_rep,
+                                 s->d_order, 1, s->d_next, m));
+            if (s->profiling) {
+                HIP_TRY(hipEventRecord(ev.b, s->stream));
+                s->ev_grow.push_back(ev);
+            }
+            done += m;
+        }
+    }
+    s->t += n;
+    s->rec_written += n;
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_synchronize(wolff_sim* s)
+{
+    if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_observables(wolff_sim* s, wolff_record* out, uint64_t cap, uint64_t* n_out)
+{
+    if (!s || (!out && cap > 0)) return fail(WOLFF_EINVAL, "NULL argument");
+    Rep r;
+    int rc = pull_rep(s, &r);
+    if (rc) return rc;
+    const uint64_t live = s->rec_written - s->rec_read;
+    const uint64_t k = std::min(cap, live);
+    if (k)
+        HIP_TRY(hipMemcpy(out, s->d_rec + s->rec_read, k * sizeof(wolff_record),
+                          hipMemcpyDeviceToHost));
+    s->rec_read += k;
+    if (n_out) *n_out = k;
+    bool push = false;
+    if (s->rec_read == s->rec_written) {
+        s->rec_read = s->rec_written = 0;
+        r.rec_count = 0;
+        push = true;
+    }
+    const uint32_t bad_bits = r.err;
+    const bool bad = bad_bits != 0u;
+    if (bad) {
+        r.err = 0u;
+        push = true;
+    }
+    if (push && (rc = push_rep(s, r))) return rc;
+    if (bad) return fail(WOLFF_ESTATE, err_message(bad_bits));
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_get_info(wolff_sim* s, wolff_info* out)
+{
+    if (!s || !out) return fail(WOLFF_EINVAL, "NULL argument");
+    Rep r;
+    int rc = pull_rep(s, &r);
+    if (rc) return rc;
+    out->dim = s->dim;
+    out->L = s->L;
+    out->n_sites = s->N;
+    out->J = s->J;
+    out->T = s->T;
+    out->seed = s->seed;
+    out->threshold = s->thr;
+    out->path = resolved_path(s);
+    out->t = r.t;
+    out->mag = r.M;
+    out->bond_sum = r.B;
+    out->records_pending = s->rec_written - s->rec_read;
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_get_spins(wolff_sim* s, int8_t* host, uint64_t n)
+{
+    if (!s || !host) return fail(WOLFF_EINVAL, "NULL argument");
+    if (n != s->N) return fail(WOLFF_EINVAL, "n must equal the number of sites");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(hipMemcpy(host, s->S, n, hipMemcpyDeviceToHost));
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_set_spins(wolff_sim* s, const int8_t* host, uint64_t n, uint64_t t)
+{
+    if (!s || !host) return fail(WOLFF_EINVAL, "NULL argument");
+    if (n != s->N) return fail(WOLFF_EINVAL, "n must equal the number of sites");
+    if (t > T_LIMIT) return fail(WOLFF_ERANGE, "t exceeds 2^32 - 2");
+    for (uint64_t i = 0; i < n; ++i)
+        if (host[i] != 1 && host[i] != -1) return fail(WOLFF_EINVAL, "spins must be +1 or -1");
+    Rep r;
+    int rc = pull_rep(s, &r);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(s->S, host, n, hipMemcpyHostToDevice));
+    r.t = (uint32_t)t;
+    r.rec_count = 0;
+    r.err = 0;
+    s->t = t;
+    s->rec_read = s->rec_written = 0;
+    if ((rc = push_rep(s, r))) return rc;
+    return measure_now(s);
+}
+
+extern "C" int wolff_set_measure(wolff_sim* s, int on)
+{
+    if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
+    Rep r;
+    int rc = pull_rep(s, &r);
+    if (rc) return rc;
+    s->measure = on ? 1 : 0;
+    r.measure = (uint32_t)s->measure;
+    return push_rep(s, r);
+}
+
+extern "C" int wolff_set_stream(wolff_sim* s, void* hip_stream)
+{
+    if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->stream = hip_stream ? (hipStream_t)hip_stream : s->own_stream;
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_set_path(wolff_sim* s, int path, int workgroups)
+{
+    if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
+    if (path != WOLFF_PATH_AUTO && path != WOLFF_PATH_SINGLE && path != WOLFF_PATH_TEAM)
+        return fail(WOLFF_EINVAL, "unknown path");
+    if (workgroups < 0 || workgroups > 65536) return fail(WOLFF_EINVAL, "bad workgroup count");
+    s->path = path;
+    s->team_wgs = workgroups;
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_profile(wolff_sim* s, int on)
+{
+    if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
+    int rc = harvest_events(s);
+    if (rc) return rc;
+    s->profiling = on != 0;
+    s->grow_ms = s->meas_ms = 0.0;
+    s->grow_n = s->meas_n = 0;
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_profile_read(wolff_sim* s, double* grow_ms, uint64_t* grow_launches,
+                                  double* measure_ms, uint64_t* measure_launches)
+{
+    if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
+    int rc = harvest_events(s);
+    if (rc) return rc;
+    if (grow_ms) *grow_ms = s->grow_ms;
+    if (grow_launches) *grow_launches = s->grow_n;
+    if (measure_ms) *measure_ms = s->meas_ms;
+    if (measure_launches) *measure_launches = s->meas_n;
+    return WOLFF_OK;
+}
+
+// ==================================================================== batch
+struct wolff_batch {
+    std::vector<wolff_job> jobs;
+    std::vector<Rep> reps;          // host copy (pointers, geometry, parameters)
+    std::vector<uint64_t> left;     // host mirror of updates left
+    std::vector<uint64_t> t;        // host mirror of next update index
+    std::vector<uint64_t> rec_read; // records drained per replica
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    int8_t* S = nullptr;            // one slab for all lattices
+    uint32_t* ov = nullptr;
+    wolff_record* rec = nullptr;
+    std::vector<uint64_t> S_off, ov_off, rec_off;
+    Rep* d_reps = nullptr;
+    uint32_t* d_order = nullptr;
+    uint32_t* d_next = nullptr;
+    std::vector<uint32_t> order;    // longest expected work first
+    int wg = 256;
+    int qentries = 2048;
+    int measure = 1;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    bool timed = false;
+};
+
+static void free_batch(wolff_batch* b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->S) (void)hipFree(b->S);
+    if (b->ov) (void)hipFree(b->ov);
+    if (b->rec) (void)hipFree(b->rec);
+    if (b->d_reps) (void)hipFree(b->d_reps);
+    if (b->d_order) (void)hipFree(b->d_order);
+    if (b->d_next) (void)hipFree(b->d_next);
+    if (b->ev_a) (void)hipEventDestroy(b->ev_a);
+    if (b->ev_b) (void)hipEventDestroy(b->ev_b);
+    if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
+    delete b;
+}
+
+extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch** out)
+{
+    if (!jobs || n_jobs <= 0 || !out) return fail(WOLFF_EINVAL, "bad job list");
+    wolff_batch* b = new (std::nothrow) wolff_batch();
+    if (!b) return fail(WOLFF_ENOMEM, "host allocation failed");
+#define BATCH_TRY(expr)                                                                 \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            int code_ = e_ == hipErrorOutOfMemory ? WOLFF_ENOMEM : WOLFF_EDEVICE;       \
+            free_batch(b);                                                              \
+            return fail(code_, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+        }                                                                               \
+    } while (0)
+    uint64_t s_total = 0, ov_total = 0, rec_total = 0;
+    std::vector<uint64_t> Ns(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) {
+        uint64_t N = 0;
+        int rc = check_params(jobs[i].dim, jobs[i].L, jobs[i].J, jobs[i].T, &N);
+        if (rc) {
+            free_batch(b);
+            return fail(rc, "job " + std::to_string(i) + ": " + g_last_error);
+        }
+        if (jobs[i].n_updates > T_LIMIT) {
+            free_batch(b);
+            return fail(WOLFF_ERANGE, "job " + std::to_string(i) + ": too many updates");
+        }
+        Ns[i] = N;
+        b->S_off.push_back(s_total);
+        b->ov_off.push_back(ov_total);
+        b->rec_off.push_back(rec_total);
+        s_total += padded_bytes(N);
+        ov_total += N;
+        rec_total += std::max<uint64_t>(jobs[i].n_updates, 1);
+    }
+    b->jobs.assign(jobs, jobs + n_jobs);
+    BATCH_TRY(hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking));
+    b->stream = b->own_stream;
+    BATCH_TRY(hipMalloc(&b->S, s_total));
+    BATCH_TRY(hipMemset(b->S, 0, s_total));
+    BATCH_TRY(hipMalloc(&b->ov, ov_total * sizeof(uint32_t)));
+    BATCH_TRY(hipMalloc(&b->rec, rec_total * sizeof(wolff_record)));
+    BATCH_TRY(hipMalloc(&b->d_reps, n_jobs * sizeof(Rep)));
+    BATCH_TRY(hipMalloc(&b->d_order, n_jobs * sizeof(uint32_t)));
+    BATCH_TRY(hipMalloc(&b->d_next, sizeof(uint32_t)));
+    BATCH_TRY(hipEventCreate(&b->ev_a));
+    BATCH_TRY(hipEventCreate(&b->ev_b));
+    b->reps.resize(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) {
+        const wolff_job& j = jobs[i];
+        Rep& r = b->reps[i];
+        r = Rep{};
+        r.S = b->S + b->S_off[i];
+        r.ov = b->ov + b->ov_off[i];
+        r.rec = b->rec + b->rec_off[i];
+        r.rec_count = 0;
+        r.geo = make_geo(j.dim, (uint32_t)j.L);
+        r.dim = j.dim;
+        r.thr = bond_threshold(j.J, j.T);
+        r.k0 = (uint32_t)j.seed;
+        r.k1 = (uint32_t)(j.seed >> 32);
+        r.t = 0;
+        r.n_left = (uint32_t)j.n_updates;
+        r.measure = 1;
+        hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((Ns[i] + 255) / 256, 65536)),
+                           dim3(256), 0, b->stream, r.S, (uint32_t)Ns[i], r.k0, r.k1);
+        BATCH_TRY(hipGetLastError());
+        b->left.push_back(j.n_updates);
+        b->t.push_back(0);
+        b->rec_read.push_back(0);
+    }
+    BATCH_TRY(hipMemcpy(b->d_reps, b->reps.data(), n_jobs * sizeof(Rep), hipMemcpyHostToDevice));
+    for (int i = 0; i < n_jobs; ++i) {
+        hipLaunchKernelGGL(wolff::measure_rep_kernel<1024>, dim3(1), dim3(1024), 0, b->stream,
+                           b->d_reps + i);
+        BATCH_TRY(hipGetLastError());
+    }
+    // longest expected work first: more sites first, colder first at equal size
+    b->order.resize(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) b->order[i] = (uint32_t)i;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](uint32_t x, uint32_t y) {
+        const double wx = (double)Ns[x] * (double)b->reps[x].thr * (double)std::max<uint64_t>(jobs[x].n_updates, 1);
+        const double wy = (double)Ns[y] * (double)b->reps[y].thr * (double)std::max<uint64_t>(jobs[y].n_updates, 1);
+        return wx > wy;
+    });
+    BATCH_TRY(hipMemcpy(b->d_order, b->order.data(), n_jobs * sizeof(uint32_t), hipMemcpyHostToDevice));
+    BATCH_TRY(hipStreamSynchronize(b->stream));
+#undef BATCH_TRY
+    *out = b;
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_batch_destroy(wolff_batch* b)
+{
+    free_batch(b);
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_batch_set_tiles(wolff_batch* b, int wg, int queue_entries)
+{
+    if (!b) return fail(WOLFF_EINVAL, "batch is NULL");
+    if (!valid_tiles(wg, queue_entries)) return fail(WOLFF_EINVAL, "unsupported tile sizes");
+    b->wg = wg;
+    b->qentries = queue_entries;
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_batch_set_measure(wolff_batch* b, int on)
+{
+    if (!b) return fail(WOLFF_EINVAL, "batch is NULL");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    std::vector<Rep> cur(b->reps.size());
+    HIP_TRY(hipMemcpy(cur.data(), b->d_reps, cur.size() * sizeof(Rep), hipMemcpyDeviceToHost));
+    b->measure = on ? 1 : 0;
+    for (auto& r : cur) r.measure = (uint32_t)b->measure;
+    HIP_TRY(hipMemcpy(b->d_reps, cur.data(), cur.size() * sizeof(Rep), hipMemcpyHostToDevice));
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_batch_set_stream(wolff_batch* b, void* hip_stream)
+{
+    if (!b) return fail(WOLFF_EINVAL, "batch is NULL");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->stream = hip_stream ? (hipStream_t)hip_stream : b->own_stream;
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_batch_run(wolff_batch* b, uint64_t max_updates)
+{
+    if (!b) return fail(WOLFF_EINVAL, "batch is NULL");
+    if (max_updates > T_LIMIT) return fail(WOLFF_EINVAL, "max_updates too large");
+    uint32_t active = 0;
+    for (size_t i = 0; i < b->jobs.size(); ++i) active += b->left[i] > 0;
+    if (active == 0) return WOLFF_OK;
+    int per_cu = 0;
+    const size_t lds = (size_t)b->qentries * sizeof(uint32_t);
+    hipError_t e;
+    switch (b->wg) {
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<64>, 64, lds); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<128>, 128, lds); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<512>, 512, lds); break;
+    case 1024: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<1024>, 1024, lds); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<256>, 256, lds); break;
+    }
+    HIP_TRY(e);
+    const uint64_t resident = (uint64_t)std::max(per_cu, 1) * (uint64_t)device_cus();
+    const uint32_t n = (uint32_t)b->jobs.size();
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(n, resident);
+    HIP_TRY(hipEventRecord(b->ev_a, b->stream));
+    HIP_TRY(launch_batch(b->wg, grid, (uint32_t)b->qentries, b->stream, b->d_reps, b->d_order, n,
+                         b->d_next, (uint32_t)max_updates));
+    HIP_TRY(hipEventRecord(b->ev_b, b->stream));
+    b->timed = true;
+    for (size_t i = 0; i < b->jobs.size(); ++i) {
+        const uint64_t m = (max_updates == 0) ? b->left[i] : std::min<uint64_t>(b->left[i], max_updates);
+        b->left[i] -= m;
+        b->t[i] += m;
+    }
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_batch_last_ms(wolff_batch* b, double* ms)
+{
+    if (!b || !ms) return fail(WOLFF_EINVAL, "NULL argument");
+    if (!b->timed) {
+        *ms = 0.0;
+        return WOLFF_OK;
+    }
+    float f = 0.0f;
+    HIP_TRY(hipEventSynchronize(b->ev_b));
+    HIP_TRY(hipEventElapsedTime(&f, b->ev_a, b->ev_b));
+    *ms = f;
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_batch_progress(wolff_batch* b, int job, uint64_t* left, uint64_t* t)
+{
+    if (!b || job < 0 || (size_t)job >= b->jobs.size()) return fail(WOLFF_EINVAL, "bad job index");
+    if (left) *left = b->left[job];
+    if (t) *t = b->t[job];
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_batch_records(wolff_batch* b, int job, wolff_record* out, uint64_t cap,
+                                   uint64_t* n_out)
+{
+    if (!b || job < 0 || (size_t)job >= b->jobs.size() || (!out && cap > 0))
+        return fail(WOLFF_EINVAL, "bad argument");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    Rep r;
+    HIP_TRY(hipMemcpy(&r, b->d_reps + job, sizeof(Rep), hipMemcpyDeviceToHost));
+    const uint64_t live = r.rec_count - b->rec_read[job];
+    const uint64_t k = std::min(cap, live);
+    if (k)
+        HIP_TRY(hipMemcpy(out, b->rec + b->rec_off[job] + b->rec_read[job],
+                          k * sizeof(wolff_record), hipMemcpyDeviceToHost));
+    b->rec_read[job] += k;
+    if (n_out) *n_out = k;
+    if (r.err) return fail(WOLFF_ESTATE, err_message(r.err));
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_batch_get_spins(wolff_batch* b, int job, int8_t* host, uint64_t n)
+{
+    if (!b || job < 0 || (size_t)job >= b->jobs.size() || !host) return fail(WOLFF_EINVAL, "bad argument");
+    const Rep& r = b->reps[job];
+    if (n != r.geo.N) return fail(WOLFF_EINVAL, "n must equal the number of sites");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    HIP_TRY(hipMemcpy(host, r.S, n, hipMemcpyDeviceToHost));
+    return WOLFF_OK;
+}

@@ -1,0 +1,204 @@
+"""GPU path against the CPU oracle, bit for bit: records (B, M, |C|) after
+every update and the final spins, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1110_0899_amd import binding, workloads
+
+pytestmark = pytest.mark.gpu
+
+TC2, T3 = workloads.TC_2D, workloads.T_3D
+
+
+def as_array(rec):
+    return np.stack([rec["bond_sum"], rec["mag"], rec["csize"]], axis=1)
+
+
+def oracle_series(dim, L, T, seed, n, t0=0, S=None):
+    thr = oracle.threshold(1.0, T)
+    if S is None:
+        S = oracle.init_spins(dim, L, seed)
+    rec = oracle.run(dim, L, thr, seed, t0, n, S)
+    return rec, S
+
+
+def gpu_series(dim, L, T, seed, n, path=binding.PATH_AUTO, team=0, measure=True):
+    print("case dim=%d L=%d T=%.6f seed=%d n=%d path=%d team=%d" % (dim, L, T, seed, n, path, team),
+          flush=True)
+    with binding.Simulation(dim, L, 1.0, T, seed) as sim:
+        sim.set_path(path, team)
+        sim.set_measure(measure)
+        sim.run(n)
+        rec = sim.observables()
+        S = sim.spins()
+        info = sim.info()
+    return as_array(rec), S, info
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available()
+    binding.load()
+
+
+def test_threshold_matches_oracle():
+    for T in (TC2, T3, 2.0, 2.6, 4.3, 4.7, 1e-3, 1e6):
+        with binding.Simulation(2, 4, 1.0, T, 1) as sim:
+            assert sim.info().threshold == oracle.threshold(1.0, T)
+
+
+def test_initial_state_matches_oracle():
+    for dim, L, seed in [(2, 32, 1), (2, 33, 9), (3, 8, 3), (3, 5, 4), (2, 1000, 5)]:
+        with binding.Simulation(dim, L, 1.0, TC2, seed) as sim:
+            S = sim.spins()
+            info = sim.info()
+        ref = oracle.init_spins(dim, L, seed)
+        assert (S == ref).all()
+        B, M = oracle.observables(dim, L, ref)
+        assert info.mag == M and info.bond_sum == B
+
+
+def test_c1_full_run_single_path():
+    c = workloads.C1
+    got, S, info = gpu_series(2, c["L"], c["T"], c["seed"], c["n_meas"], binding.PATH_SINGLE)
+    ref, Sref = oracle_series(2, c["L"], c["T"], c["seed"], c["n_meas"])
+    assert got.shape == ref.shape
+    bad = np.nonzero((got != ref).any(axis=1))[0]
+    assert bad.size == 0, "first mismatch at update %d: %s vs %s" % (bad[0], got[bad[0]], ref[bad[0]])
+    assert (S == Sref).all()
+    assert info.t == c["n_meas"]
+
+
+SMALL_CASES = [
+    (2, 2, 2.0, 300), (2, 3, TC2, 300), (2, 17, 1.8, 300), (2, 64, TC2, 300), (2, 100, 2.6, 200),
+    (3, 2, T3, 300), (3, 3, 4.0, 300), (3, 8, T3, 300), (3, 13, 4.7, 200), (3, 32, T3, 100),
+]
+
+
+def check_small(path, dim, L, T, n):
+    seed = 100 + L
+    got, S, _ = gpu_series(dim, L, T, seed, n, path, 8)
+    ref, Sref = oracle_series(dim, L, T, seed, n)
+    bad = np.nonzero((got != ref).any(axis=1))[0]
+    assert bad.size == 0, "first mismatch at update %d: %s vs %s" % (bad[0], got[bad[0]], ref[bad[0]])
+    assert (S == Sref).all()
+
+
+def check_cold(path):
+    # T well below T_c from the ordered state: clusters cover most of the
+    # lattice, the frontier outgrows the LDS ring and the overflow stack /
+    # global queue is used.
+    for dim, L, T, n in [(2, 256, 1.5, 30), (3, 40, 3.0, 20)]:
+        N = L ** dim
+        start = np.ones(N, dtype=np.int8)
+        print("case cold dim=%d L=%d T=%.3f path=%d" % (dim, L, T, path), flush=True)
+        with binding.Simulation(dim, L, 1.0, T, 77) as sim:
+            sim.set_path(path, 32)
+            sim.set_spins(start, 0)
+            sim.run(n)
+            got = as_array(sim.observables())
+            S = sim.spins()
+        ref, Sref = oracle_series(dim, L, T, 77, n, S=start.copy())
+        assert (got == ref).all()
+        assert (S == Sref).all()
+        assert ref[:, 2].max() > N // 2
+
+
+def test_update_only_mode():
+    got, S, _ = gpu_series(2, 32, TC2, 5, 500, binding.PATH_SINGLE, measure=False)
+    ref, Sref = oracle_series(2, 32, TC2, 5, 500)
+    assert (got[:, 0] == binding.NOT_MEASURED).all()
+    assert (got[:, 1:] == ref[:, 1:]).all()
+    assert (S == Sref).all()
+    got, S, _ = gpu_series(3, 8, T3, 5, 200, binding.PATH_TEAM, 8, measure=False)
+    ref, Sref = oracle_series(3, 8, T3, 5, 200)
+    assert (got[:, 0] == binding.NOT_MEASURED).all()
+    assert (got[:, 1:] == ref[:, 1:]).all()
+
+
+def test_split_runs_and_resume():
+    dim, L, T, seed = 2, 48, TC2, 31
+    ref, Sref = oracle_series(dim, L, T, seed, 600)
+    with binding.Simulation(dim, L, 1.0, T, seed) as sim:
+        sim.run(100)
+        sim.run(150)
+        a = as_array(sim.observables())
+        mid = sim.spins()
+        sim.run(50)
+        b = as_array(sim.observables())
+    assert (np.concatenate([a, b]) == ref[:300]).all()
+    # resume in a fresh handle from the checkpoint (spins, t)
+    with binding.Simulation(dim, L, 1.0, T, 999) as sim2:
+        pass
+    with binding.Simulation(dim, L, 1.0, T, seed) as sim3:
+        sim3.set_spins(mid, 250)
+        sim3.run(350)
+        c = as_array(sim3.observables())
+        assert (c == ref[250:]).all()
+        assert (sim3.spins() == Sref).all()
+
+
+def test_range_error():
+    with binding.Simulation(2, 4, 1.0, TC2, 1) as sim:
+        sim.set_spins(np.ones(16, dtype=np.int8), 0xFFFFFFFE - 3)
+        sim.run(3)
+        with pytest.raises(binding.WolffError) as e:
+            sim.run(2)
+        assert e.value.code == binding.ERANGE
+
+
+def test_special_cases():
+    # T -> infinity: no active bond, |C| = 1
+    got, _, _ = gpu_series(2, 16, 1e30, 3, 200)
+    assert (got[:, 2] == 1).all()
+    # T -> 0 from all up: the cluster is the whole lattice
+    with binding.Simulation(3, 6, 1.0, 1e-3, 4) as sim:
+        sim.set_spins(np.ones(216, dtype=np.int8), 0)
+        sim.run(10)
+        got = as_array(sim.observables())
+    assert (got[:, 2] == 216).all() and (got[:, 0] == 3 * 216).all()
+
+
+def test_batch_matches_alone():
+    jobs = [workloads.Job(2, 32, TC2, 11, 400), workloads.Job(3, 8, T3, 12, 300),
+            workloads.Job(2, 17, 2.5, 13, 350), workloads.Job(2, 128, 2.0, 14, 60),
+            workloads.Job(3, 5, 4.0, 15, 500), workloads.Job(2, 2, 1.0, 16, 100)]
+    with binding.Batch(jobs) as b:
+        b.run(150)                      # one launch, at most 150 updates each
+        b.run()                          # the rest
+        for i, j in enumerate(jobs):
+            got = as_array(b.records(i))
+            ref, Sref = oracle_series(j.dim, j.L, j.T, j.seed, j.n_updates)
+            assert (got == ref).all(), i
+            assert (b.spins(i) == Sref).all(), i
+
+
+# ---- one-workgroup path
+@pytest.mark.parametrize("dim,L,T,n", SMALL_CASES)
+def test_small_lattices_single(dim, L, T, n):
+    check_small(binding.PATH_SINGLE, dim, L, T, n)
+
+
+def test_cold_lattice_single():
+    check_cold(binding.PATH_SINGLE)
+
+
+# ---- multi-workgroup team path
+def test_c1_team_path():
+    c = workloads.C1
+    n = 2000
+    got, S, _ = gpu_series(2, c["L"], c["T"], c["seed"], n, binding.PATH_TEAM, 16)
+    ref, Sref = oracle_series(2, c["L"], c["T"], c["seed"], n)
+    assert (got == ref).all()
+    assert (S == Sref).all()
+
+
+@pytest.mark.parametrize("dim,L,T,n", SMALL_CASES)
+def test_small_lattices_team(dim, L, T, n):
+    check_small(binding.PATH_TEAM, dim, L, T, n)
+
+
+def test_cold_lattice_team():
+    check_cold(binding.PATH_TEAM)
