@@ -1,0 +1,263 @@
+"""Benchmark of the Wolff single-cluster hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs plain2d,plain3d,batch2d,batch3d]
+
+A step is one Wolff update of the whole hot path (seed draw, frontier growth
+with bond activation, claim-and-flip, E/M measurement, record) on the
+workload's lattice.  The headline workload is the square lattice L = 4096 at
+T_c = 2/ln(1+sqrt 2) through the plain one-lattice launch path; the other
+legs (simple-cubic L = 256, and the batched persistent form on both) are
+reported under "extra".  Inputs are synthetic (seeded, no dataset).
+
+Prints ONE JSON line.  `value` is added spins per second (sum of cluster
+sizes over the timed updates / wall time between synchronisations).
+`roofline` prices the dominant kernel (cluster growth) at the algorithmic
+bytes per added spin (2d neighbour gathers + 8 B claim + 1 B flip + 8 B
+queue write/read = 21 B in 2D, 23 B in 3D) against the 8 TB/s HBM peak,
+timed per launch with HIP events on the stream the kernel runs on.
+`cpu_baseline` times the CPU oracle (one core) on a bounded sample of the
+same workload: it replays updates from the GPU's thermalised state, and its
+records are compared with the GPU's for those updates.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_ADDED = {2: 21.0, 3: 23.0}
+PAPER_CONTEXT = {
+    "2d_L4096": "paper: 5.60x over one Xeon W3520 core (GTX 285, 83.95 ms/update incl. measurement)",
+    "3d_L256": "paper: 7.90x over one Xeon W3520 core (GTX 285, 17.45 ms/update incl. measurement)",
+}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1110_0899_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "counters_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def ordered_start(n_sites: int) -> np.ndarray:
+    return np.ones(n_sites, dtype=np.int8)
+
+
+def plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered=True):
+    """Plain one-lattice path: warmup updates, then `steps` timed updates."""
+    import torch
+    sim = binding.Simulation(dim, L, 1.0, T, seed)
+    sim.set_measure(True)
+    if start_ordered:
+        sim.set_spins(ordered_start(L ** dim), 0)
+    t0 = time.time()
+    sim.run(warmup)
+    sim.synchronize()
+    sim.observables()
+    log("%dD L=%d: %d warmup updates in %.1f s" % (dim, L, warmup, time.time() - t0))
+    checkpoint = sim.spins()
+    t_ckpt = sim.info().t
+    sim.profile(True)
+    torch.cuda.synchronize()
+    sim.synchronize()
+    a = time.perf_counter()
+    sim.run(steps)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - a
+    rec = sim.observables()
+    prof = sim.profile_read()
+    info = sim.info()
+    sim.close()
+    added = int(rec["csize"].sum())
+    grow_ms = prof["grow_ms"]
+    achieved = BYTES_PER_ADDED[dim] * added / (grow_ms * 1e-3) / 1e9 if grow_ms > 0 else 0.0
+    log("%dD L=%d: %d updates in %.2f s, <|C|>=%.0f, %.3e added/s, grow %.3f ms/launch"
+        % (dim, L, steps, wall, added / max(steps, 1), added / wall,
+           grow_ms / max(prof["grow_launches"], 1)))
+    return {
+        "dim": dim, "L": L, "T": T, "seed": seed, "warmup": warmup, "steps": steps,
+        "wall_s": wall, "added": added, "added_per_s": added / wall,
+        "updates_per_s": steps / wall, "mean_csize": added / max(steps, 1),
+        "grow_ms": grow_ms, "grow_launches": prof["grow_launches"],
+        "measure_ms": prof["measure_ms"], "measure_launches": prof["measure_launches"],
+        "grow_GBs_algorithmic": achieved, "path": int(info.path),
+        "records": rec, "checkpoint": checkpoint, "t_ckpt": t_ckpt,
+    }
+
+
+def batch_leg(binding, workloads, dim, L, n_rep, warmup, steps, wg=256, q=2048):
+    """Batched persistent form: n_rep same-shape replicas at T_c, one launch
+    per run; warmup updates, then `steps` timed updates of every replica."""
+    jobs = workloads.same_shape_jobs(dim, L, n_rep, warmup + steps)
+    b = binding.Batch(jobs, start=1)
+    b.set_tiles(wg, q)
+    b.set_measure(True)
+    t0 = time.time()
+    b.run(warmup)
+    b.last_ms()
+    log("batch %dD L=%d x%d: %d warmup updates in %.1f s" % (dim, L, n_rep, warmup, time.time() - t0))
+    for i in range(n_rep):
+        b.records(i)
+    a = time.perf_counter()
+    b.run(steps)
+    ms = b.last_ms()
+    wall = time.perf_counter() - a
+    added = 0
+    for i in range(n_rep):
+        added += int(b.records(i)["csize"].sum())
+    b.close()
+    kernel_s = ms * 1e-3
+    log("batch %dD L=%d x%d: %d updates each in %.2f s (kernel %.2f s), %.3e added/s"
+        % (dim, L, n_rep, steps, wall, kernel_s, added / kernel_s))
+    return {
+        "dim": dim, "L": L, "replicas": n_rep, "warmup": warmup, "steps": steps, "wg": wg,
+        "queue_entries": q, "wall_s": wall, "kernel_s": kernel_s, "added": added,
+        "added_per_s": added / wall, "updates_per_s": n_rep * steps / wall,
+        "mean_csize": added / (n_rep * steps),
+        "kernel_GBs_algorithmic": BYTES_PER_ADDED[dim] * added / kernel_s / 1e9,
+    }
+
+
+def cpu_baseline(leg, budget_s=15.0):
+    """The CPU oracle (one core) replaying updates from the GPU checkpoint."""
+    import oracle
+    dim, L, T, seed = leg["dim"], leg["L"], leg["T"], leg["seed"]
+    thr = oracle.threshold(1.0, T)
+    S = leg["checkpoint"].copy()
+    t = leg["t_ckpt"]
+    gpu = leg["records"]
+    done, added, match = 0, 0, True
+    a = time.perf_counter()
+    while done < len(gpu) and time.perf_counter() - a < budget_s:
+        rec = oracle.run(dim, L, thr, seed, t + done, 1, S)
+        g = gpu[done]
+        match &= (int(g["bond_sum"]), int(g["mag"]), int(g["csize"])) == tuple(int(v) for v in rec[0])
+        added += int(rec[0, 2])
+        done += 1
+    el = time.perf_counter() - a
+    log("cpu oracle: %d updates in %.1f s, %.3e added/s, records match GPU: %s"
+        % (done, el, added / el, match))
+    return {
+        "value": added / el, "unit": "added spins/s", "cores": 1, "kind": "oracle",
+        "sample": "%d consecutive updates of the %dD L=%d workload replayed from the GPU's "
+                  "thermalised state (update %d on), full E/M recount per update"
+                  % (done, dim, L, leg["t_ckpt"]),
+        "updates": done, "seconds": el, "records_match_gpu": bool(match),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000, help="timed updates of the headline leg")
+    ap.add_argument("--warmup", type=int, default=1000, help="thermalisation updates")
+    ap.add_argument("--legs", default="plain2d,plain3d,batch2d,batch3d")
+    ap.add_argument("--batch-replicas", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(independent lattices would shard across GPUs with no exchange).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1110_0899_amd import binding, workloads
+
+    assert torch.cuda.is_available(), "needs a GPU"
+    torch.cuda.set_device(0)
+    binding.load()
+    legs = [s.strip() for s in args.legs.split(",") if s.strip()]
+    extra = {"context": PAPER_CONTEXT}
+
+    main_leg = plain_leg(binding, 2, 4096, workloads.TC_2D, 2, args.warmup, args.steps)
+    cpu = cpu_baseline(main_leg, args.cpu_seconds)
+    if "plain3d" in legs:
+        l3 = plain_leg(binding, 3, 256, workloads.T_3D, 3, 3 * args.warmup, 5 * args.steps)
+        extra["plain_3d_L256"] = {k: v for k, v in l3.items()
+                                  if k not in ("records", "checkpoint")}
+    if "batch2d" in legs:
+        extra["batch_2d_L4096"] = batch_leg(binding, workloads, 2, 4096, args.batch_replicas,
+                                            args.warmup // 4, args.batch_steps)
+        extra["batch_2d_L4096"]["vs_plain"] = (extra["batch_2d_L4096"]["added_per_s"]
+                                               / main_leg["added_per_s"])
+    if "batch3d" in legs:
+        extra["batch_3d_L256"] = batch_leg(binding, workloads, 3, 256, args.batch_replicas,
+                                           args.warmup, 5 * args.batch_steps)
+        if "plain_3d_L256" in extra:
+            extra["batch_3d_L256"]["vs_plain"] = (extra["batch_3d_L256"]["added_per_s"]
+                                                  / extra["plain_3d_L256"]["added_per_s"])
+
+    achieved = main_leg["grow_GBs_algorithmic"]
+    traffic = counter_traffic("team_kernel", "2d_L4096")
+    out = {
+        "metric": "added spins/s at Tc, 2D L=4096 & 3D L=256; % HBM peak; batched vs plain",
+        "value": main_leg["added_per_s"],
+        "unit": "added spins/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * main_leg["wall_s"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8 spins, u32 Philox draws, int64 sums",
+        "data": "synthetic (seeded lattices; no dataset)",
+        "config": {
+            "workload": "2d_L4096_Tc_plain",
+            "dim": 2, "L": 4096, "T": workloads.TC_2D, "J": 1.0, "seed": 2,
+            "start": "ordered, thermalised for `warmup` updates at T_c",
+            "path": "plain one-lattice launch path (multi-workgroup team kernel)",
+            "measurement": "E and M after every update",
+            "mean_cluster_size": main_leg["mean_csize"],
+            "updates_per_s": main_leg["updates_per_s"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "team_kernel (cluster growth)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "bytes_per_added_spin": BYTES_PER_ADDED[2],
+            "launches": main_leg["grow_launches"],
+            "avg_launch_ms": main_leg["grow_ms"] / max(main_leg["grow_launches"], 1),
+        },
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -155,7 +155,10 @@ typedef struct {
     double   J;
     double   T;
     uint64_t seed;
-    uint64_t n_updates;      /* updates this replica still has to run */
+    uint64_t n_updates;      /* updates this replica still has to run        */
+    int32_t  start;          /* initial spins: 0 iid +-1 from seed (as in
+                                wolff_create), +1 all up, -1 all down         */
+    int32_t  reserved;       /* must be 0                                     */
 } wolff_job;
 
 typedef struct wolff_batch wolff_batch;

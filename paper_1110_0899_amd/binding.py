@@ -45,7 +45,8 @@ class Info(ctypes.Structure):
 
 class JobDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("L", ctypes.c_int32), ("J", ctypes.c_double),
-                ("T", ctypes.c_double), ("seed", ctypes.c_uint64), ("n_updates", ctypes.c_uint64)]
+                ("T", ctypes.c_double), ("seed", ctypes.c_uint64), ("n_updates", ctypes.c_uint64),
+                ("start", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 RECORD_DTYPE = np.dtype([("bond_sum", np.int64), ("mag", np.int64), ("csize", np.int64)])
@@ -203,11 +204,14 @@ class Simulation:
 class Batch:
     """Many replicas advanced by one persistent launch per run()."""
 
-    def __init__(self, jobs):
+    def __init__(self, jobs, start: int = 0):
+        """jobs: objects with dim, L, J, T, seed, n_updates; start: 0 iid +-1
+        from each seed, +1 / -1 ordered."""
         lib = load()
         arr = (JobDesc * len(jobs))()
         for i, j in enumerate(jobs):
-            arr[i] = JobDesc(j.dim, j.L, float(j.J), float(j.T), int(j.seed), int(j.n_updates))
+            arr[i] = JobDesc(j.dim, j.L, float(j.J), float(j.T), int(j.seed), int(j.n_updates),
+                             int(start), 0)
         h = ctypes.c_void_p()
         _check(lib.wolff_batch_create(arr, len(jobs), ctypes.byref(h)), "wolff_batch_create")
         self._h = h

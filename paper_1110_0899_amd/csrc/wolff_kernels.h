@@ -48,8 +48,8 @@ struct TeamCtl {
     int32_t s0;             // seed spin before the update
     uint32_t pad;
     unsigned long long csize;
-    long long accB;         // measurement accumulators
-    long long accM;
+    long long acc_diff;     // measurement: differing bonds
+    long long acc_neg;      // measurement: negative spins
     uint32_t blocks_done;
     uint32_t pad2;
 };

@@ -77,36 +77,86 @@ __device__ __forceinline__ uint32_t wave_compact(const bool won[2 * DIM], uint32
 }
 
 // ------------------------------------------------------------- reductions
-// B = sum_i sum_mu S_i S_{i+e_mu} and M = sum_i S_i over one lattice by one
-// workgroup; coordinates advance incrementally (no division in the loop).
-template <int WG, int DIM>
-__device__ void reduce_lattice_wg(const int8_t* S, const Geo& g, long long* red,
-                                  int64_t& Bout, int64_t& Mout)
+// B = sum_i sum_mu S_i S_{i+e_mu} and M = sum_i S_i.
+//
+// Vector form (L a multiple of 16): a chunk is 16 consecutive sites of one
+// row, read as one 16-byte load.  With +1 = 0x01 and -1 = 0xFF, bit 1 of a
+// byte is set exactly for -1, and bit 1 of (a ^ b) is set exactly when two
+// spins differ, so per chunk
+//   differing bonds = popcount(((a ^ shifted neighbour bytes) & 0x02020202))
+//   negative spins  = popcount(a & 0x02020202)
+// and over the lattice B = d N - 2 (differing bonds), M = N - 2 (negatives).
+// The +x neighbours are the chunk shifted by one byte plus the first byte of
+// the next chunk of the row (wrapping to the row start); +y / +z are the
+// chunks one row / one plane further (periodic).
+template <int DIM>
+__device__ __forceinline__ void chunk_counts(const int8_t* S, const Geo& g, uint32_t c,
+                                             uint32_t& ndiff, uint32_t& nneg)
 {
-    constexpr int NW = WG / WAVE;
-    const uint32_t tid = threadIdx.x;
+    const uint4* S4 = reinterpret_cast<const uint4*>(S);
+    const uint32_t* S1 = reinterpret_cast<const uint32_t*>(S);
     const uint32_t L = g.L, N = g.N, LL = g.LL;
-    const uint32_t q0 = g.div_L(tid);
-    uint32_t x = tid - q0 * L;
+    const uint32_t i = c * 16u;
+    const uint32_t q = g.div_L(i);
+    const uint32_t x0 = i - q * L;
+    const uint4 a = S4[c];
+    const uint32_t inext = (x0 + 16u == L) ? i + 16u - L : i + 16u;
+    const uint32_t w4 = S1[inext >> 2];
+    const uint32_t K = 0x02020202u;
+    const uint32_t s0 = (a.x >> 8) | (a.y << 24);
+    const uint32_t s1 = (a.y >> 8) | (a.z << 24);
+    const uint32_t s2 = (a.z >> 8) | (a.w << 24);
+    const uint32_t s3 = (a.w >> 8) | (w4 << 24);
+    uint32_t d = __popc((a.x ^ s0) & K) + __popc((a.y ^ s1) & K) + __popc((a.z ^ s2) & K) +
+                 __popc((a.w ^ s3) & K);
+    uint32_t iy;
+    if (DIM == 2) {
+        iy = (i >= N - L) ? i - (N - L) : i + L;
+    } else {
+        const uint32_t y = q - g.div_L(q) * L;
+        iy = (y + 1u == L) ? i + L - LL : i + L;
+    }
+    const uint4 b = S4[iy >> 4];
+    d += __popc((a.x ^ b.x) & K) + __popc((a.y ^ b.y) & K) + __popc((a.z ^ b.z) & K) +
+         __popc((a.w ^ b.w) & K);
+    if (DIM == 3) {
+        const uint32_t iz = (i >= N - LL) ? i - (N - LL) : i + LL;
+        const uint4 z = S4[iz >> 4];
+        d += __popc((a.x ^ z.x) & K) + __popc((a.y ^ z.y) & K) + __popc((a.z ^ z.z) & K) +
+             __popc((a.w ^ z.w) & K);
+    }
+    ndiff = d;
+    nneg = __popc(a.x & K) + __popc(a.y & K) + __popc(a.z & K) + __popc(a.w & K);
+}
+
+// Scalar form for any L: per site, with coordinates advanced incrementally
+// along the thread's stride (no division in the loop).  Accumulates the same
+// two counts as the vector form.
+template <int DIM>
+__device__ __forceinline__ void scalar_counts(const int8_t* S, const Geo& g, uint32_t first,
+                                              uint32_t stride, uint32_t& ndiff, uint32_t& nneg)
+{
+    const uint32_t L = g.L, N = g.N, LL = g.LL;
+    const uint32_t q0 = g.div_L(first);
+    uint32_t x = first - q0 * L;
     uint32_t y = q0 - g.div_L(q0) * L;
-    const uint32_t dq = g.div_L((uint32_t)WG);
-    const uint32_t dx = (uint32_t)WG - dq * L;
+    const uint32_t dq = g.div_L(stride);
+    const uint32_t dx = stride - dq * L;
     const uint32_t dq_mod = dq - g.div_L(dq) * L;
-    int32_t b = 0, m = 0;
-    for (uint32_t i = tid; i < N; i += WG) {
-        const int si = S[i];
+    uint32_t d = 0u, neg = 0u;
+    for (uint32_t i = first; i < N; i += stride) {
+        const int8_t si = S[i];
         const uint32_t xp = (x + 1u == L) ? i + 1u - L : i + 1u;
-        int nsum = S[xp];
+        d += (S[xp] != si);
         if (DIM == 2) {
             const uint32_t yp = (i >= N - L) ? i - (N - L) : i + L;
-            nsum += S[yp];
+            d += (S[yp] != si);
         } else {
             const uint32_t yp = (y + 1u == L) ? i + L - LL : i + L;
             const uint32_t zp = (i >= N - LL) ? i - (N - LL) : i + LL;
-            nsum += S[yp] + S[zp];
+            d += (S[yp] != si) + (S[zp] != si);
         }
-        b += si * nsum;
-        m += si;
+        neg += (si < 0);
         x += dx;
         uint32_t carry = 0u;
         if (x >= L) {
@@ -118,23 +168,78 @@ __device__ void reduce_lattice_wg(const int8_t* S, const Geo& g, long long* red,
             if (y >= L) y -= L;
         }
     }
-    const int64_t wb = wave_sum_i64((int64_t)b);
-    const int64_t wm = wave_sum_i64((int64_t)m);
+    ndiff = d;
+    nneg = neg;
+}
+
+// This thread's counts over its share of the lattice: items first, first +
+// stride, ... (chunks when L % 16 == 0, sites otherwise).
+template <int DIM>
+__device__ __forceinline__ void lattice_counts(const int8_t* S, const Geo& g, uint32_t first,
+                                               uint32_t stride, uint64_t& ndiff, uint64_t& nneg)
+{
+    uint64_t d = 0u, neg = 0u;
+    if ((g.L & 15u) == 0u) {
+        const uint32_t nchunks = g.N >> 4;
+        uint32_t c = first;
+        for (; c + 3u * stride < nchunks; c += 4u * stride) {        // 4 chunks in flight
+            uint32_t d0, n0, d1, n1, d2, n2, d3, n3;
+            chunk_counts<DIM>(S, g, c, d0, n0);
+            chunk_counts<DIM>(S, g, c + stride, d1, n1);
+            chunk_counts<DIM>(S, g, c + 2u * stride, d2, n2);
+            chunk_counts<DIM>(S, g, c + 3u * stride, d3, n3);
+            d += d0 + d1 + d2 + d3;
+            neg += n0 + n1 + n2 + n3;
+        }
+        for (; c < nchunks; c += stride) {
+            uint32_t d0, n0;
+            chunk_counts<DIM>(S, g, c, d0, n0);
+            d += d0;
+            neg += n0;
+        }
+    } else {
+        uint32_t d0 = 0u, n0 = 0u;
+        if (first < g.N) scalar_counts<DIM>(S, g, first, stride, d0, n0);
+        d = d0;
+        neg = n0;
+    }
+    ndiff = d;
+    nneg = neg;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// (B, M) of one lattice by one workgroup; every thread receives the result.
+template <int WG, int DIM>
+__device__ void reduce_lattice_wg(const int8_t* S, const Geo& g, long long* red,
+                                  int64_t& Bout, int64_t& Mout)
+{
+    constexpr int NW = WG / WAVE;
+    const uint32_t tid = threadIdx.x;
+    uint64_t d, neg;
+    lattice_counts<DIM>(S, g, tid, WG, d, neg);
+    d = wave_sum_u64(d);
+    neg = wave_sum_u64(neg);
     const uint32_t wv = tid / WAVE;
     __syncthreads();
     if ((tid & (WAVE - 1)) == 0) {
-        red[wv] = wb;
-        red[NW + wv] = wm;
+        red[wv] = (long long)d;
+        red[NW + wv] = (long long)neg;
     }
     __syncthreads();
-    int64_t sb = 0, sm = 0;
+    int64_t sd = 0, sn = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-        sb += red[w];
-        sm += red[NW + w];
+        sd += red[w];
+        sn += red[NW + w];
     }
-    Bout = sb;
-    Mout = sm;
+    Bout = (int64_t)DIM * (int64_t)g.N - 2 * sd;
+    Mout = (int64_t)g.N - 2 * sn;
     __syncthreads();
 }
 
@@ -338,8 +443,8 @@ __global__ void team_seed_kernel(Rep* R, TeamCtl* ctl, unsigned long long* gq)
     ctl->pending = 1;
     ctl->exited = 0u;
     ctl->csize = 1ull;
-    ctl->accB = 0;
-    ctl->accM = 0;
+    ctl->acc_diff = 0;
+    ctl->acc_neg = 0;
     ctl->blocks_done = 0u;
     gq[0] = ((unsigned long long)epoch << 32) | s;
 }
@@ -510,48 +615,30 @@ __global__ __launch_bounds__(256) void measure_grid_kernel(Rep* R, TeamCtl* ctl)
     constexpr int WG = 256, NW = WG / WAVE;
     __shared__ long long red[2 * NW];
     const Geo g = R->geo;
-    const int8_t* S = R->S;
-    const uint32_t L = g.L, N = g.N, LL = g.LL;
-    int32_t b = 0, m = 0;
-    const uint32_t stride = gridDim.x * WG;
-    for (uint32_t i = blockIdx.x * WG + threadIdx.x; i < N; i += stride) {
-        const uint32_t q = g.div_L(i);
-        const uint32_t x = i - q * L;
-        const int si = S[i];
-        const uint32_t xp = (x + 1u == L) ? i + 1u - L : i + 1u;
-        int nsum = S[xp];
-        if (DIM == 2) {
-            const uint32_t yp = (i >= N - L) ? i - (N - L) : i + L;
-            nsum += S[yp];
-        } else {
-            const uint32_t y = q - g.div_L(q) * L;
-            const uint32_t yp = (y + 1u == L) ? i + L - LL : i + L;
-            const uint32_t zp = (i >= N - LL) ? i - (N - LL) : i + LL;
-            nsum += S[yp] + S[zp];
-        }
-        b += si * nsum;
-        m += si;
-    }
-    const int64_t wb = wave_sum_i64((int64_t)b);
-    const int64_t wm = wave_sum_i64((int64_t)m);
+    uint64_t d, neg;
+    lattice_counts<DIM>(R->S, g, blockIdx.x * WG + threadIdx.x, gridDim.x * WG, d, neg);
+    d = wave_sum_u64(d);
+    neg = wave_sum_u64(neg);
     if ((threadIdx.x & (WAVE - 1)) == 0) {
-        red[threadIdx.x / WAVE] = wb;
-        red[NW + threadIdx.x / WAVE] = wm;
+        red[threadIdx.x / WAVE] = (long long)d;
+        red[NW + threadIdx.x / WAVE] = (long long)neg;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int64_t sb = 0, sm = 0;
+        long long sd = 0, sn = 0;
         for (int w = 0; w < NW; ++w) {
-            sb += red[w];
-            sm += red[NW + w];
+            sd += red[w];
+            sn += red[NW + w];
         }
-        __hip_atomic_fetch_add(&ctl->accB, (long long)sb, __ATOMIC_RELAXED, SCOPE_AGENT);
-        __hip_atomic_fetch_add(&ctl->accM, (long long)sm, __ATOMIC_RELAXED, SCOPE_AGENT);
+        __hip_atomic_fetch_add(&ctl->acc_diff, sd, __ATOMIC_RELAXED, SCOPE_AGENT);
+        __hip_atomic_fetch_add(&ctl->acc_neg, sn, __ATOMIC_RELAXED, SCOPE_AGENT);
         const uint32_t prev =
             __hip_atomic_fetch_add(&ctl->blocks_done, 1u, __ATOMIC_ACQ_REL, SCOPE_AGENT);
         if (prev == gridDim.x - 1u) {
-            const int64_t B = __hip_atomic_load(&ctl->accB, __ATOMIC_RELAXED, SCOPE_AGENT);
-            const int64_t Mm = __hip_atomic_load(&ctl->accM, __ATOMIC_RELAXED, SCOPE_AGENT);
+            const long long td = __hip_atomic_load(&ctl->acc_diff, __ATOMIC_RELAXED, SCOPE_AGENT);
+            const long long tn = __hip_atomic_load(&ctl->acc_neg, __ATOMIC_RELAXED, SCOPE_AGENT);
+            const int64_t B = (int64_t)DIM * (int64_t)g.N - 2 * (int64_t)td;
+            const int64_t Mm = (int64_t)g.N - 2 * (int64_t)tn;
             const int64_t M = R->M;
             if (Mm != M) R->err |= ERR_MAG;
             R->B = B;

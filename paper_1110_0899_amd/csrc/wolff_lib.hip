@@ -432,7 +432,11 @@ static int run_team_update(wolff_sim* s)
             if (rc) return rc;
             HIP_TRY(hipEventRecord(em.a, s->stream));
         }
-        const uint32_t blocks = (uint32_t)std::min<uint64_t>((s->N + 255) / 256, 4096);
+        // a few blocks per CU, each thread loops over its chunks: the per-block
+        // atomics of the final reduction stay few
+        const uint64_t items = ((s->L & 15) == 0) ? s->N / 16 : s->N;
+        const uint32_t blocks = (uint32_t)std::max<uint64_t>(
+            1, std::min<uint64_t>((items + 1023) / 1024, (uint64_t)device_cus() * 2));
         if (s->dim == 2)
             hipLaunchKernelGGL(wolff::measure_grid_kernel<2>, dim3(blocks), dim3(256), 0, s->stream, s->d_rep, s->d_ctl);
         else
@@ -686,6 +690,10 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
             free_batch(b);
             return fail(rc, "job " + std::to_string(i) + ": " + g_last_error);
         }
+        if (jobs[i].start < -1 || jobs[i].start > 1 || jobs[i].reserved != 0) {
+            free_batch(b);
+            return fail(WOLFF_EINVAL, "job " + std::to_string(i) + ": bad start or reserved field");
+        }
         if (jobs[i].n_updates > T_LIMIT) {
             free_batch(b);
             return fail(WOLFF_ERANGE, "job " + std::to_string(i) + ": too many updates");
@@ -727,9 +735,13 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
         r.t = 0;
         r.n_left = (uint32_t)j.n_updates;
         r.measure = 1;
-        hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((Ns[i] + 255) / 256, 65536)),
-                           dim3(256), 0, b->stream, r.S, (uint32_t)Ns[i], r.k0, r.k1);
-        BATCH_TRY(hipGetLastError());
+        if (j.start == 0) {
+            hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((Ns[i] + 255) / 256, 65536)),
+                               dim3(256), 0, b->stream, r.S, (uint32_t)Ns[i], r.k0, r.k1);
+            BATCH_TRY(hipGetLastError());
+        } else {
+            BATCH_TRY(hipMemsetAsync(r.S, j.start > 0 ? 0x01 : 0xFF, Ns[i], b->stream));
+        }
         b->left.push_back(j.n_updates);
         b->t.push_back(0);
         b->rec_read.push_back(0);
