@@ -175,6 +175,36 @@ def cpu_baseline(leg, budget_s=15.0):
     }
 
 
+def profile_only(args, binding, workloads):
+    """One leg alone, for rocprofv3 runs (kernel trace or counters)."""
+    import torch
+    leg = args.profile_leg
+    if leg == "copy":
+        # calibration for the HBM counters: one device-to-device copy of 1 GiB
+        n = 1 << 30
+        a = torch.ones(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        r = {"leg": "copy", "bytes_read": n, "bytes_written": n}
+    elif leg == "plain2d":
+        r = plain_leg(binding, 2, 4096, workloads.TC_2D, 2, args.warmup, args.steps)
+    elif leg == "plain3d":
+        r = plain_leg(binding, 3, 256, workloads.T_3D, 3, args.warmup, args.steps)
+    elif leg == "batch2d":
+        r = batch_leg(binding, workloads, 2, 4096, args.batch_replicas, args.warmup,
+                      args.batch_steps)
+    elif leg == "batch3d":
+        r = batch_leg(binding, workloads, 3, 256, args.batch_replicas, args.warmup,
+                      args.batch_steps)
+    else:
+        raise SystemExit("unknown leg %s" % leg)
+    r = {k: v for k, v in r.items() if k not in ("records", "checkpoint")}
+    r["leg"] = leg
+    print(json.dumps(r), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +214,9 @@ def main():
     ap.add_argument("--batch-replicas", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile-leg", default=None,
+                    help="run only this leg (plain2d, plain3d, batch2d, batch3d, copy) for a "
+                         "profiler; prints that leg's numbers instead of the benchmark line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -198,6 +231,10 @@ def main():
     binding.load()
     legs = [s.strip() for s in args.legs.split(",") if s.strip()]
     extra = {"context": PAPER_CONTEXT}
+
+    if args.profile_leg:
+        profile_only(args, binding, workloads)
+        return
 
     main_leg = plain_leg(binding, 2, 4096, workloads.TC_2D, 2, args.warmup, args.steps)
     cpu = cpu_baseline(main_leg, args.cpu_seconds)
