@@ -147,6 +147,24 @@ def batch_leg(binding, workloads, dim, L, n_rep, warmup, steps, wg=256, q=2048):
     }
 
 
+def serve_leg(workloads, quantum_ms=5.0, n_jobs=2000, max_wall_s=20.0):
+    """Serving form: capacity from a closed batch of stream jobs, then the
+    Poisson stream at 1.2x that rate through the continuous-batching loop."""
+    from paper_1110_0899_amd import serve
+    sample = workloads.c5_stream(n_jobs=200, rate_per_s=1.0, seed=55)
+    cap = serve.capacity(sample, quantum_ms)
+    rate = 1.2 * cap
+    stream = workloads.c5_stream(n_jobs=n_jobs, rate_per_s=rate)
+    r = serve.run_stream(stream, quantum_ms=quantum_ms, max_wall_s=max_wall_s)
+    r.pop("records", None)
+    r.update({"capacity_jobs_per_s": cap, "arrival_rate_jobs_per_s": rate,
+              "quantum_ms": quantum_ms})
+    log("serve: capacity %.1f jobs/s, stream at %.1f jobs/s: %d jobs, p50 %.3f s, p99 %.3f s, "
+        "%.3e added/s" % (cap, rate, r["jobs"], r["p50_latency_s"], r["p99_latency_s"],
+                          r["added_per_s"]))
+    return r
+
+
 def cpu_baseline(leg, budget_s=15.0):
     """The CPU oracle (one core) replaying updates from the GPU checkpoint."""
     import oracle
@@ -210,7 +228,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000, help="timed updates of the headline leg")
     ap.add_argument("--warmup", type=int, default=1000, help="thermalisation updates")
-    ap.add_argument("--legs", default="plain2d,plain3d,batch2d,batch3d")
+    ap.add_argument("--legs", default="plain2d,plain3d,batch2d,batch3d,serve")
     ap.add_argument("--batch-replicas", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -253,6 +271,9 @@ def main():
         if "plain_3d_L256" in extra:
             extra["batch_3d_L256"]["vs_plain"] = (extra["batch_3d_L256"]["added_per_s"]
                                                   / extra["plain_3d_L256"]["added_per_s"])
+
+    if "serve" in legs:
+        extra["serve_stream"] = serve_leg(workloads)
 
     achieved = main_leg["grow_GBs_algorithmic"]
     traffic = counter_traffic("team_kernel", "2d_L4096")

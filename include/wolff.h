@@ -192,6 +192,65 @@ int wolff_batch_set_tiles(wolff_batch *b, int wg, int queue_entries);
  * the batch's stream; synchronises), and the number of launches it made. */
 int wolff_batch_last_ms(wolff_batch *b, double *ms);
 
+/* ------------------------------------------------------------ serving loop */
+/* A request loop that keeps lattices resident in HBM and advances every
+ * resident job in time-bounded quanta, each one persistent launch of the
+ * batched kernel (continuous batching).  Jobs are admitted first-in
+ * first-out while a workgroup slot and their HBM footprint are free
+ * (footprint = spins + overflow stack + records: about 5 N + 24 n_updates
+ * bytes); a job submitted while others run joins the next quantum, so its
+ * updates overlap with theirs on the device.  Every job's records are
+ * exactly those of the same job run alone (the random stream is keyed by the
+ * job's own seed and update index, never by its neighbours in the batch).
+ * A finished job's records move to host memory and its HBM is released. */
+typedef struct wolff_server wolff_server;
+
+#define WOLFF_JOB_QUEUED  0
+#define WOLFF_JOB_RUNNING 1
+#define WOLFF_JOB_DONE    2
+#define WOLFF_JOB_FAILED  3   /* a device consistency check failed for the job */
+
+typedef struct {
+    uint64_t queued;         /* submitted, not admitted                     */
+    uint64_t running;        /* resident on the device                      */
+    uint64_t done;           /* finished, records not yet taken             */
+    uint64_t slots;          /* most jobs resident at once                  */
+    uint64_t resident_bytes; /* HBM held by resident jobs                   */
+    uint64_t budget_bytes;   /* HBM admission budget                        */
+    uint64_t quanta;         /* launches so far                             */
+    uint64_t updates;        /* updates completed over all jobs             */
+    uint64_t added_spins;    /* sum of cluster sizes over those updates     */
+    double   gpu_ms;         /* summed kernel time of the quanta            */
+} wolff_server_stats;
+
+/* hbm_budget_bytes: admission budget (0 = 80 % of the free device memory);
+ * max_slots: most resident jobs (0 = workgroups resident at once). */
+int wolff_server_create(uint64_t hbm_budget_bytes, int max_slots, wolff_server **out);
+int wolff_server_destroy(wolff_server *srv);
+
+/* Queue a job (start field as in wolff_job); *job_id identifies it.
+ * WOLFF_EINVAL for bad parameters or a footprint above the whole budget. */
+int wolff_server_submit(wolff_server *srv, const wolff_job *job, uint64_t *job_id);
+
+/* One scheduling iteration: admit queued jobs that fit, run one quantum of
+ * about quantum_ms (every resident job advances by whole updates until the
+ * quantum is spent or it finishes), retire finished jobs.  Synchronous.
+ * *n_finished receives the number of jobs that finished in this step. */
+int wolff_server_step(wolff_server *srv, double quantum_ms, uint64_t *n_finished);
+
+/* State (WOLFF_JOB_*) and updates done of one job. */
+int wolff_server_status(wolff_server *srv, uint64_t job_id, int *state, uint64_t *updates_done);
+
+/* Ids of jobs finished since the previous call (up to cap). */
+int wolff_server_finished(wolff_server *srv, uint64_t *ids, uint64_t cap, uint64_t *n_out);
+
+/* Records of a finished job (oldest first, up to cap); the job is forgotten
+ * once all its records have been taken. */
+int wolff_server_take(wolff_server *srv, uint64_t job_id, wolff_record *out, uint64_t cap,
+                      uint64_t *n_out);
+
+int wolff_server_get_stats(wolff_server *srv, wolff_server_stats *out);
+
 #ifdef __cplusplus
 }
 #endif

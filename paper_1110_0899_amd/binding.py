@@ -49,6 +49,16 @@ class JobDesc(ctypes.Structure):
                 ("start", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_uint64), ("running", ctypes.c_uint64), ("done", ctypes.c_uint64),
+                ("slots", ctypes.c_uint64), ("resident_bytes", ctypes.c_uint64),
+                ("budget_bytes", ctypes.c_uint64), ("quanta", ctypes.c_uint64),
+                ("updates", ctypes.c_uint64), ("added_spins", ctypes.c_uint64),
+                ("gpu_ms", ctypes.c_double)]
+
+
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
+
 RECORD_DTYPE = np.dtype([("bond_sum", np.int64), ("mag", np.int64), ("csize", np.int64)])
 
 # name -> (restype, argtypes); every symbol declared in include/wolff.h
@@ -83,6 +93,14 @@ SIGNATURES = {
     "wolff_batch_set_stream": (_I, [_P, _P]),
     "wolff_batch_set_tiles": (_I, [_P, _I, _I]),
     "wolff_batch_last_ms": (_I, [_P, ctypes.POINTER(_D)]),
+    "wolff_server_create": (_I, [_U64, _I, ctypes.POINTER(_P)]),
+    "wolff_server_destroy": (_I, [_P]),
+    "wolff_server_submit": (_I, [_P, ctypes.POINTER(JobDesc), ctypes.POINTER(_U64)]),
+    "wolff_server_step": (_I, [_P, _D, ctypes.POINTER(_U64)]),
+    "wolff_server_status": (_I, [_P, _U64, ctypes.POINTER(_I), ctypes.POINTER(_U64)]),
+    "wolff_server_finished": (_I, [_P, _P, _U64, ctypes.POINTER(_U64)]),
+    "wolff_server_take": (_I, [_P, _U64, _P, _U64, ctypes.POINTER(_U64)]),
+    "wolff_server_get_stats": (_I, [_P, ctypes.POINTER(ServerStats)]),
 }
 
 _lib = None
@@ -273,3 +291,73 @@ class Batch:
         ms = _D()
         _check(load().wolff_batch_last_ms(self._h, ctypes.byref(ms)), "wolff_batch_last_ms")
         return ms.value
+
+
+class Server:
+    """Continuous-batching request loop (wolff_server_*)."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, max_slots: int = 0):
+        h = ctypes.c_void_p()
+        _check(load().wolff_server_create(int(hbm_budget_bytes), int(max_slots), ctypes.byref(h)),
+               "wolff_server_create")
+        self._h = h
+        self.n_updates = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().wolff_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, job, start: int = 0) -> int:
+        d = JobDesc(job.dim, job.L, float(job.J), float(job.T), int(job.seed), int(job.n_updates),
+                    int(start), 0)
+        jid = _U64()
+        _check(load().wolff_server_submit(self._h, ctypes.byref(d), ctypes.byref(jid)),
+               "wolff_server_submit")
+        self.n_updates[jid.value] = int(job.n_updates)
+        return jid.value
+
+    def step(self, quantum_ms: float) -> int:
+        n = _U64()
+        _check(load().wolff_server_step(self._h, float(quantum_ms), ctypes.byref(n)),
+               "wolff_server_step")
+        return n.value
+
+    def status(self, job_id: int):
+        st, done = ctypes.c_int(), _U64()
+        _check(load().wolff_server_status(self._h, int(job_id), ctypes.byref(st), ctypes.byref(done)),
+               "wolff_server_status")
+        return st.value, done.value
+
+    def finished(self, cap: int = 4096) -> list:
+        ids = np.zeros(cap, dtype=np.uint64)
+        n = _U64()
+        _check(load().wolff_server_finished(self._h, ids.ctypes.data, cap, ctypes.byref(n)),
+               "wolff_server_finished")
+        return [int(v) for v in ids[: n.value]]
+
+    def take(self, job_id: int) -> np.ndarray:
+        cap = max(self.n_updates.get(job_id, 1), 1)
+        out = np.zeros(cap, dtype=RECORD_DTYPE)
+        n = _U64()
+        _check(load().wolff_server_take(self._h, int(job_id), out.ctypes.data, cap, ctypes.byref(n)),
+               "wolff_server_take")
+        self.n_updates.pop(job_id, None)
+        return out[: n.value]
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().wolff_server_get_stats(self._h, ctypes.byref(st)), "wolff_server_get_stats")
+        return {name: getattr(st, name) for name, _ in ServerStats._fields_}

@@ -249,9 +249,25 @@ __device__ void reduce_lattice_wg(const int8_t* S, const Geo& g, long long* red,
 // the lattice's global overflow stack and come back when the ring runs low.
 // Items are appended in whole steps: ballot/mbcnt inside each wave, a prefix
 // over the waves' counts in LDS, one store per new site.
+// Workgroup-shared control words of the one-workgroup path.
+struct WgCtl {
+    int s0;                 // seed spin of the current update
+    uint32_t stop;          // 1: the launch's time budget is spent
+    uint32_t idx;           // next replica (work counter)
+    uint32_t pad;
+    uint64_t t_start;       // wall clock at the workgroup's start
+};
+
+// Time budget of a launch, checked by thread 0 only and broadcast through
+// LDS so that every thread of the workgroup takes the same decision.
+__device__ __forceinline__ uint32_t budget_spent(const WgCtl* c, uint64_t budget)
+{
+    return (budget != 0u && wall_clock64() - c->t_start >= budget) ? 1u : 0u;
+}
+
 template <int WG, int DIM>
-__device__ void run_rep(Rep* R, uint32_t max_updates, uint32_t qmask, uint32_t* q,
-                        uint32_t* wave_cnt, long long* red, int* sh_s0)
+__device__ void run_rep(Rep* R, uint32_t max_updates, uint64_t budget, uint32_t qmask,
+                        uint32_t* q, uint32_t* wave_cnt, long long* red, WgCtl* ctl)
 {
     constexpr int NW = WG / WAVE;
     const uint32_t tid = threadIdx.x;
@@ -271,17 +287,19 @@ __device__ void run_rep(Rep* R, uint32_t max_updates, uint32_t qmask, uint32_t* 
     uint32_t err = 0u;
     const uint32_t QC = qmask + 1u;
 
-    for (uint32_t u = 0; u < n; ++u) {
+    uint32_t done = 0u;
+    while (done < n) {
+        const uint32_t u = done;
         const uint32_t t = t0 + u;
         const uint32_t s = seed_site(k0, k1, t, g.N);             // step (i)
         if (tid == 0) {
             const int s0 = S[s];
             claim<SCOPE_WG>(S, s, s0);
             q[0] = s;
-            *sh_s0 = s0;
+            ctl->s0 = s0;
         }
         __syncthreads();
-        const int s0 = *sh_s0;
+        const int s0 = ctl->s0;
 
         uint32_t head = 0u, tail = 1u, ovn = 0u;                    // the paper's in / ic
         uint64_t csize = 1u;
@@ -343,39 +361,55 @@ __device__ void run_rep(Rep* R, uint32_t max_updates, uint32_t qmask, uint32_t* 
             r.mag = M;
             r.csize = (int64_t)csize;
             rec[u] = r;
+            ctl->stop = budget_spent(ctl, budget);
         }
         __syncthreads();
+        ++done;
+        if (ctl->stop) break;                 // at an update boundary only
     }
     if (tid == 0) {
-        R->t = t0 + n;
-        R->n_left -= n;
-        R->rec_count += n;
+        R->t = t0 + done;
+        R->n_left -= done;
+        R->rec_count += done;
         R->M = M;
         R->B = B;
         R->err |= err;
     }
 }
 
+// Persistent batched form: workgroup w starts with replica order[w] and then
+// takes order[gridDim.x + atomicAdd(next)] until the list or the time budget
+// (wall-clock ticks, 0 = none) is exhausted.  A replica is only ever
+// advanced by one workgroup per launch, so its claims are workgroup-scope;
+// the kernel boundary publishes its state to the next launch.
 template <int WG>
 __global__ __launch_bounds__(WG) void batch_kernel(Rep* reps, const uint32_t* order,
                                                    uint32_t n_reps, uint32_t* next,
-                                                   uint32_t max_updates, uint32_t qmask)
+                                                   uint32_t max_updates, uint32_t qmask,
+                                                   uint64_t budget)
 {
     extern __shared__ uint32_t q[];
     __shared__ uint32_t wave_cnt[WG / WAVE];
     __shared__ long long red[2 * (WG / WAVE)];
-    __shared__ int sh_s0;
-    __shared__ uint32_t sh_idx;
+    __shared__ WgCtl ctl;
+    if (threadIdx.x == 0) {
+        ctl.t_start = wall_clock64();
+        ctl.stop = 0u;
+    }
+    __syncthreads();
     uint32_t idx = blockIdx.x;
     while (idx < n_reps) {
         Rep* R = reps + order[idx];
         if (R->dim == 2)
-            run_rep<WG, 2>(R, max_updates, qmask, q, wave_cnt, red, &sh_s0);
+            run_rep<WG, 2>(R, max_updates, budget, qmask, q, wave_cnt, red, &ctl);
         else
-            run_rep<WG, 3>(R, max_updates, qmask, q, wave_cnt, red, &sh_s0);
-        if (threadIdx.x == 0) sh_idx = gridDim.x + atomicAdd(next, 1u);
+            run_rep<WG, 3>(R, max_updates, budget, qmask, q, wave_cnt, red, &ctl);
+        if (threadIdx.x == 0) {
+            ctl.stop = budget_spent(&ctl, budget);
+            ctl.idx = ctl.stop ? n_reps : gridDim.x + atomicAdd(next, 1u);
+        }
         __syncthreads();
-        idx = sh_idx;
+        idx = ctl.idx;
         __syncthreads();
     }
 }
@@ -654,11 +688,11 @@ __global__ __launch_bounds__(256) void measure_grid_kernel(Rep* R, TeamCtl* ctl)
 }
 
 // explicit instantiations used by the host code
-template __global__ void batch_kernel<64>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t);
-template __global__ void batch_kernel<128>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t);
-template __global__ void batch_kernel<256>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t);
-template __global__ void batch_kernel<512>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t);
-template __global__ void batch_kernel<1024>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t);
+template __global__ void batch_kernel<64>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<128>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<256>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<512>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<1024>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
 template __global__ void measure_rep_kernel<1024>(Rep*);
 template __global__ void team_kernel<256, 2>(Rep*, TeamCtl*, unsigned long long*, uint32_t, uint32_t);
 template __global__ void team_kernel<256, 3>(Rep*, TeamCtl*, unsigned long long*, uint32_t, uint32_t);

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -125,26 +127,27 @@ static int device_cus()
 }
 
 static hipError_t launch_batch(int wg, uint32_t grid, uint32_t qentries, hipStream_t st, Rep* reps,
-                               const uint32_t* order, uint32_t n, uint32_t* next, uint32_t max_updates)
+                               const uint32_t* order, uint32_t n, uint32_t* next, uint32_t max_updates,
+                               uint64_t budget = 0)
 {
     const size_t lds = (size_t)qentries * sizeof(uint32_t);
     const uint32_t qmask = qentries - 1u;
     hipLaunchKernelGGL(wolff::reset_counter_kernel, dim3(1), dim3(64), 0, st, next);
     switch (wg) {
     case 64:
-        hipLaunchKernelGGL(wolff::batch_kernel<64>, dim3(grid), dim3(64), lds, st, reps, order, n, next, max_updates, qmask);
+        hipLaunchKernelGGL(wolff::batch_kernel<64>, dim3(grid), dim3(64), lds, st, reps, order, n, next, max_updates, qmask, budget);
         break;
     case 128:
-        hipLaunchKernelGGL(wolff::batch_kernel<128>, dim3(grid), dim3(128), lds, st, reps, order, n, next, max_updates, qmask);
+        hipLaunchKernelGGL(wolff::batch_kernel<128>, dim3(grid), dim3(128), lds, st, reps, order, n, next, max_updates, qmask, budget);
         break;
     case 512:
-        hipLaunchKernelGGL(wolff::batch_kernel<512>, dim3(grid), dim3(512), lds, st, reps, order, n, next, max_updates, qmask);
+        hipLaunchKernelGGL(wolff::batch_kernel<512>, dim3(grid), dim3(512), lds, st, reps, order, n, next, max_updates, qmask, budget);
         break;
     case 1024:
-        hipLaunchKernelGGL(wolff::batch_kernel<1024>, dim3(grid), dim3(1024), lds, st, reps, order, n, next, max_updates, qmask);
+        hipLaunchKernelGGL(wolff::batch_kernel<1024>, dim3(grid), dim3(1024), lds, st, reps, order, n, next, max_updates, qmask, budget);
         break;
     default:
-        hipLaunchKernelGGL(wolff::batch_kernel<256>, dim3(grid), dim3(256), lds, st, reps, order, n, next, max_updates, qmask);
+        hipLaunchKernelGGL(wolff::batch_kernel<256>, dim3(grid), dim3(256), lds, st, reps, order, n, next, max_updates, qmask, budget);
         break;
     }
     return hipGetLastError();
@@ -884,5 +887,322 @@ extern "C" int wolff_batch_get_spins(wolff_batch* b, int job, int8_t* host, uint
     if (n != r.geo.N) return fail(WOLFF_EINVAL, "n must equal the number of sites");
     HIP_TRY(hipStreamSynchronize(b->stream));
     HIP_TRY(hipMemcpy(host, r.S, n, hipMemcpyDeviceToHost));
+    return WOLFF_OK;
+}
+
+// ================================================================== server
+// Continuous-batching request loop over the batched kernel.  Host-side
+// state per job; device memory per job is one stream-ordered allocation
+// (spins | overflow stack | records).
+namespace {
+
+struct SrvJob {
+    wolff_job spec{};
+    uint64_t id = 0;
+    int state = WOLFF_JOB_QUEUED;
+    uint64_t N = 0;
+    uint64_t footprint = 0;
+    void* block = nullptr;
+    Rep rep{};
+    bool fresh = false;                 // admitted, initial (B, M) not measured yet
+    std::vector<wolff_record> results;  // records of a finished job
+    uint64_t taken = 0;
+};
+
+uint64_t job_footprint(uint64_t N, uint64_t n_updates)
+{
+    return padded_bytes(N) + ((4 * N + 255) & ~uint64_t(255)) +
+           std::max<uint64_t>(n_updates, 1) * sizeof(wolff_record) + 256;
+}
+
+int batch_occupancy(int wg, int qentries)
+{
+    int per_cu = 0;
+    const size_t lds = (size_t)qentries * sizeof(uint32_t);
+    hipError_t e;
+    switch (wg) {
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<64>, 64, lds); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<128>, 128, lds); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<512>, 512, lds); break;
+    case 1024: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<1024>, 1024, lds); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<256>, 256, lds); break;
+    }
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    return per_cu * device_cus();
+}
+
+}  // namespace
+
+struct wolff_server {
+    hipStream_t stream = nullptr;
+    uint64_t budget = 0;
+    uint64_t resident = 0;
+    uint64_t slots = 0;
+    int wg = 256;
+    int qentries = 2048;
+    uint64_t ticks_per_ms = 100000;     // wall-clock counter rate
+    uint64_t next_id = 1;
+    std::map<uint64_t, SrvJob> jobs;
+    std::deque<uint64_t> queue;
+    std::vector<uint64_t> running;      // slot order of the last quantum
+    std::vector<uint64_t> finished;     // finished since the last query
+    Rep* h_reps = nullptr;              // pinned staging of the descriptors
+    Rep* d_reps = nullptr;
+    uint32_t* d_order = nullptr;
+    uint32_t* d_next = nullptr;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    uint64_t quanta = 0, updates = 0, added = 0;
+    double gpu_ms = 0.0;
+};
+
+static void free_server(wolff_server* v)
+{
+    if (!v) return;
+    if (v->stream) {
+        for (auto& kv : v->jobs)
+            if (kv.second.block) (void)hipFreeAsync(kv.second.block, v->stream);
+        (void)hipStreamSynchronize(v->stream);
+    }
+    if (v->h_reps) (void)hipHostFree(v->h_reps);
+    if (v->d_reps) (void)hipFree(v->d_reps);
+    if (v->d_order) (void)hipFree(v->d_order);
+    if (v->d_next) (void)hipFree(v->d_next);
+    if (v->ev_a) (void)hipEventDestroy(v->ev_a);
+    if (v->ev_b) (void)hipEventDestroy(v->ev_b);
+    if (v->stream) (void)hipStreamDestroy(v->stream);
+    delete v;
+}
+
+extern "C" int wolff_server_create(uint64_t hbm_budget_bytes, int max_slots, wolff_server** out)
+{
+    if (!out || max_slots < 0) return fail(WOLFF_EINVAL, "bad argument");
+    wolff_server* v = new (std::nothrow) wolff_server();
+    if (!v) return fail(WOLFF_ENOMEM, "host allocation failed");
+#define SRV_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            int code_ = e_ == hipErrorOutOfMemory ? WOLFF_ENOMEM : WOLFF_EDEVICE;       \
+            free_server(v);                                                             \
+            return fail(code_, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+        }                                                                               \
+    } while (0)
+    SRV_TRY(hipStreamCreateWithFlags(&v->stream, hipStreamNonBlocking));
+    if (hbm_budget_bytes == 0) {
+        size_t free_b = 0, total_b = 0;
+        SRV_TRY(hipMemGetInfo(&free_b, &total_b));
+        hbm_budget_bytes = (uint64_t)(0.8 * (double)free_b);
+    }
+    v->budget = hbm_budget_bytes;
+    const int cap = batch_occupancy(v->wg, v->qentries);
+    v->slots = (max_slots > 0) ? (uint64_t)std::min(max_slots, cap) : (uint64_t)cap;
+    int dev = 0, khz = 0;
+    SRV_TRY(hipGetDevice(&dev));
+    SRV_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz > 0) v->ticks_per_ms = (uint64_t)khz;
+    SRV_TRY(hipHostMalloc((void**)&v->h_reps, v->slots * sizeof(Rep), hipHostMallocDefault));
+    SRV_TRY(hipMalloc(&v->d_reps, v->slots * sizeof(Rep)));
+    SRV_TRY(hipMalloc(&v->d_order, v->slots * sizeof(uint32_t)));
+    SRV_TRY(hipMalloc(&v->d_next, sizeof(uint32_t)));
+    {
+        std::vector<uint32_t> ident(v->slots);
+        for (uint64_t i = 0; i < v->slots; ++i) ident[i] = (uint32_t)i;
+        SRV_TRY(hipMemcpy(v->d_order, ident.data(), v->slots * sizeof(uint32_t), hipMemcpyHostToDevice));
+    }
+    SRV_TRY(hipEventCreate(&v->ev_a));
+    SRV_TRY(hipEventCreate(&v->ev_b));
+#undef SRV_TRY
+    *out = v;
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_server_destroy(wolff_server* v)
+{
+    free_server(v);
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_server_submit(wolff_server* v, const wolff_job* job, uint64_t* job_id)
+{
+    if (!v || !job || !job_id) return fail(WOLFF_EINVAL, "NULL argument");
+    uint64_t N = 0;
+    int rc = check_params(job->dim, job->L, job->J, job->T, &N);
+    if (rc) return rc;
+    if (job->start < -1 || job->start > 1 || job->reserved != 0)
+        return fail(WOLFF_EINVAL, "bad start or reserved field");
+    if (job->n_updates > T_LIMIT) return fail(WOLFF_ERANGE, "too many updates");
+    SrvJob j;
+    j.spec = *job;
+    j.id = v->next_id++;
+    j.N = N;
+    j.footprint = job_footprint(N, job->n_updates);
+    if (j.footprint > v->budget) return fail(WOLFF_EINVAL, "job footprint exceeds the HBM budget");
+    const uint64_t id = j.id;
+    v->jobs.emplace(id, std::move(j));
+    v->queue.push_back(id);
+    *job_id = id;
+    return WOLFF_OK;
+}
+
+// Admit queued jobs in arrival order while a slot and the footprint are free.
+static int server_admit(wolff_server* v)
+{
+    while (!v->queue.empty() && v->running.size() < v->slots) {
+        SrvJob& j = v->jobs.at(v->queue.front());
+        if (v->resident + j.footprint > v->budget) break;            // strict FIFO
+        void* blk = nullptr;
+        HIP_TRY(hipMallocAsync(&blk, j.footprint, v->stream));
+        j.block = blk;
+        int8_t* S = (int8_t*)blk;
+        uint32_t* ov = (uint32_t*)((char*)blk + padded_bytes(j.N));
+        wolff_record* rec = (wolff_record*)((char*)ov + ((4 * j.N + 255) & ~uint64_t(255)));
+        HIP_TRY(hipMemsetAsync(S, 0, padded_bytes(j.N), v->stream));
+        if (j.spec.start == 0) {
+            hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((j.N + 255) / 256, 65536)),
+                               dim3(256), 0, v->stream, S, (uint32_t)j.N, (uint32_t)j.spec.seed,
+                               (uint32_t)(j.spec.seed >> 32));
+            HIP_TRY(hipGetLastError());
+        } else {
+            HIP_TRY(hipMemsetAsync(S, j.spec.start > 0 ? 0x01 : 0xFF, j.N, v->stream));
+        }
+        Rep& r = j.rep;
+        r = Rep{};
+        r.S = S;
+        r.ov = ov;
+        r.rec = rec;
+        r.rec_count = 0;
+        r.geo = make_geo(j.spec.dim, (uint32_t)j.spec.L);
+        r.dim = j.spec.dim;
+        r.thr = bond_threshold(j.spec.J, j.spec.T);
+        r.k0 = (uint32_t)j.spec.seed;
+        r.k1 = (uint32_t)(j.spec.seed >> 32);
+        r.t = 0;
+        r.n_left = (uint32_t)j.spec.n_updates;
+        r.measure = 1;
+        j.fresh = true;
+        j.state = WOLFF_JOB_RUNNING;
+        v->resident += j.footprint;
+        v->running.push_back(j.id);
+        v->queue.pop_front();
+    }
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_server_step(wolff_server* v, double quantum_ms, uint64_t* n_finished)
+{
+    if (!v || !(quantum_ms >= 0.0)) return fail(WOLFF_EINVAL, "bad argument");
+    int rc = server_admit(v);
+    if (rc) return rc;
+    uint64_t fin = 0;
+    const uint32_t n = (uint32_t)v->running.size();
+    if (n > 0) {
+        for (uint32_t i = 0; i < n; ++i) v->h_reps[i] = v->jobs.at(v->running[i]).rep;
+        HIP_TRY(hipMemcpyAsync(v->d_reps, v->h_reps, n * sizeof(Rep), hipMemcpyHostToDevice, v->stream));
+        for (uint32_t i = 0; i < n; ++i) {
+            SrvJob& j = v->jobs.at(v->running[i]);
+            if (j.fresh) {
+                hipLaunchKernelGGL(wolff::measure_rep_kernel<1024>, dim3(1), dim3(1024), 0, v->stream,
+                                   v->d_reps + i);
+                HIP_TRY(hipGetLastError());
+                j.fresh = false;
+            }
+        }
+        const uint64_t budget = (uint64_t)(quantum_ms * (double)v->ticks_per_ms);
+        HIP_TRY(hipEventRecord(v->ev_a, v->stream));
+        HIP_TRY(launch_batch(v->wg, n, (uint32_t)v->qentries, v->stream, v->d_reps, v->d_order, n,
+                             v->d_next, 0u, budget == 0 ? 1 : budget));
+        HIP_TRY(hipEventRecord(v->ev_b, v->stream));
+        HIP_TRY(hipMemcpyAsync(v->h_reps, v->d_reps, n * sizeof(Rep), hipMemcpyDeviceToHost, v->stream));
+        HIP_TRY(hipStreamSynchronize(v->stream));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, v->ev_a, v->ev_b));
+        v->gpu_ms += ms;
+        v->quanta += 1;
+        std::vector<uint64_t> still;
+        still.reserve(n);
+        for (uint32_t i = 0; i < n; ++i) {
+            SrvJob& j = v->jobs.at(v->running[i]);
+            const Rep before = j.rep;
+            j.rep = v->h_reps[i];
+            v->updates += j.rep.t - before.t;
+            if (j.rep.n_left == 0 || j.rep.err) {
+                const uint64_t cnt = j.rep.rec_count;
+                j.results.resize(cnt);
+                if (cnt)
+                    HIP_TRY(hipMemcpy(j.results.data(), j.rep.rec, cnt * sizeof(wolff_record),
+                                      hipMemcpyDeviceToHost));
+                for (const auto& r : j.results) v->added += (uint64_t)r.csize;
+                HIP_TRY(hipFreeAsync(j.block, v->stream));
+                j.block = nullptr;
+                v->resident -= j.footprint;
+                j.state = j.rep.err ? WOLFF_JOB_FAILED : WOLFF_JOB_DONE;
+                v->finished.push_back(j.id);
+                ++fin;
+            } else {
+                still.push_back(j.id);
+            }
+        }
+        v->running.swap(still);
+    }
+    if (n_finished) *n_finished = fin;
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_server_status(wolff_server* v, uint64_t job_id, int* state, uint64_t* updates_done)
+{
+    if (!v) return fail(WOLFF_EINVAL, "server is NULL");
+    auto it = v->jobs.find(job_id);
+    if (it == v->jobs.end()) return fail(WOLFF_EINVAL, "unknown job id");
+    if (state) *state = it->second.state;
+    if (updates_done) *updates_done = it->second.rep.t;
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_server_finished(wolff_server* v, uint64_t* ids, uint64_t cap, uint64_t* n_out)
+{
+    if (!v || (!ids && cap > 0)) return fail(WOLFF_EINVAL, "bad argument");
+    const uint64_t k = std::min<uint64_t>(cap, v->finished.size());
+    for (uint64_t i = 0; i < k; ++i) ids[i] = v->finished[i];
+    v->finished.erase(v->finished.begin(), v->finished.begin() + (ptrdiff_t)k);
+    if (n_out) *n_out = k;
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_server_take(wolff_server* v, uint64_t job_id, wolff_record* out, uint64_t cap,
+                                 uint64_t* n_out)
+{
+    if (!v || (!out && cap > 0)) return fail(WOLFF_EINVAL, "bad argument");
+    auto it = v->jobs.find(job_id);
+    if (it == v->jobs.end()) return fail(WOLFF_EINVAL, "unknown job id");
+    SrvJob& j = it->second;
+    if (j.state != WOLFF_JOB_DONE && j.state != WOLFF_JOB_FAILED)
+        return fail(WOLFF_EINVAL, "job has not finished");
+    const uint64_t k = std::min<uint64_t>(cap, j.results.size() - j.taken);
+    if (k) std::memcpy(out, j.results.data() + j.taken, k * sizeof(wolff_record));
+    j.taken += k;
+    if (n_out) *n_out = k;
+    const bool failed = j.state == WOLFF_JOB_FAILED;
+    const std::string msg = failed ? err_message(j.rep.err) : std::string();
+    if (j.taken == j.results.size()) v->jobs.erase(it);
+    if (failed) return fail(WOLFF_ESTATE, msg);
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_server_get_stats(wolff_server* v, wolff_server_stats* out)
+{
+    if (!v || !out) return fail(WOLFF_EINVAL, "NULL argument");
+    out->queued = v->queue.size();
+    out->running = v->running.size();
+    uint64_t done = 0;
+    for (const auto& kv : v->jobs)
+        done += kv.second.state == WOLFF_JOB_DONE || kv.second.state == WOLFF_JOB_FAILED;
+    out->done = done;
+    out->slots = v->slots;
+    out->resident_bytes = v->resident;
+    out->budget_bytes = v->budget;
+    out->quanta = v->quanta;
+    out->updates = v->updates;
+    out->added_spins = v->added;
+    out->gpu_ms = v->gpu_ms;
     return WOLFF_OK;
 }
