@@ -158,8 +158,12 @@ typedef struct {
     uint64_t n_updates;      /* updates this replica still has to run        */
     int32_t  start;          /* initial spins: 0 iid +-1 from seed (as in
                                 wolff_create), +1 all up, -1 all down         */
-    int32_t  reserved;       /* must be 0                                     */
+    int32_t  flags;          /* 0, or WOLFF_JOB_UPDATE_ONLY: records carry
+                                bond_sum = WOLFF_NOT_MEASURED (the paper's
+                                "update only"); mag and csize stay exact      */
 } wolff_job;
+
+#define WOLFF_JOB_UPDATE_ONLY 1
 
 typedef struct wolff_batch wolff_batch;
 
@@ -228,7 +232,7 @@ typedef struct {
 int wolff_server_create(uint64_t hbm_budget_bytes, int max_slots, wolff_server **out);
 int wolff_server_destroy(wolff_server *srv);
 
-/* Queue a job (start field as in wolff_job); *job_id identifies it.
+/* Queue a job (start and flags as in wolff_job); *job_id identifies it.
  * WOLFF_EINVAL for bad parameters or a footprint above the whole budget. */
 int wolff_server_submit(wolff_server *srv, const wolff_job *job, uint64_t *job_id);
 

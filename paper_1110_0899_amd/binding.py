@@ -46,7 +46,10 @@ class Info(ctypes.Structure):
 class JobDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("L", ctypes.c_int32), ("J", ctypes.c_double),
                 ("T", ctypes.c_double), ("seed", ctypes.c_uint64), ("n_updates", ctypes.c_uint64),
-                ("start", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("start", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+JOB_UPDATE_ONLY = 1
 
 
 class ServerStats(ctypes.Structure):
@@ -222,14 +225,15 @@ class Simulation:
 class Batch:
     """Many replicas advanced by one persistent launch per run()."""
 
-    def __init__(self, jobs, start: int = 0):
+    def __init__(self, jobs, start: int = 0, update_only: bool = False):
         """jobs: objects with dim, L, J, T, seed, n_updates; start: 0 iid +-1
-        from each seed, +1 / -1 ordered."""
+        from each seed, +1 / -1 ordered; update_only: no bond sum per update."""
         lib = load()
         arr = (JobDesc * len(jobs))()
+        flags = JOB_UPDATE_ONLY if update_only else 0
         for i, j in enumerate(jobs):
             arr[i] = JobDesc(j.dim, j.L, float(j.J), float(j.T), int(j.seed), int(j.n_updates),
-                             int(start), 0)
+                             int(start), flags)
         h = ctypes.c_void_p()
         _check(lib.wolff_batch_create(arr, len(jobs), ctypes.byref(h)), "wolff_batch_create")
         self._h = h
@@ -320,9 +324,9 @@ class Server:
     def __exit__(self, *exc):
         self.close()
 
-    def submit(self, job, start: int = 0) -> int:
+    def submit(self, job, start: int = 0, update_only: bool = False) -> int:
         d = JobDesc(job.dim, job.L, float(job.J), float(job.T), int(job.seed), int(job.n_updates),
-                    int(start), 0)
+                    int(start), JOB_UPDATE_ONLY if update_only else 0)
         jid = _U64()
         _check(load().wolff_server_submit(self._h, ctypes.byref(d), ctypes.byref(jid)),
                "wolff_server_submit")

@@ -693,9 +693,9 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
             free_batch(b);
             return fail(rc, "job " + std::to_string(i) + ": " + g_last_error);
         }
-        if (jobs[i].start < -1 || jobs[i].start > 1 || jobs[i].reserved != 0) {
+        if (jobs[i].start < -1 || jobs[i].start > 1 || (jobs[i].flags & ~WOLFF_JOB_UPDATE_ONLY) != 0) {
             free_batch(b);
-            return fail(WOLFF_EINVAL, "job " + std::to_string(i) + ": bad start or reserved field");
+            return fail(WOLFF_EINVAL, "job " + std::to_string(i) + ": bad start or flags field");
         }
         if (jobs[i].n_updates > T_LIMIT) {
             free_batch(b);
@@ -737,7 +737,7 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
         r.k1 = (uint32_t)(j.seed >> 32);
         r.t = 0;
         r.n_left = (uint32_t)j.n_updates;
-        r.measure = 1;
+        r.measure = (j.flags & WOLFF_JOB_UPDATE_ONLY) ? 0u : 1u;
         if (j.start == 0) {
             hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((Ns[i] + 255) / 256, 65536)),
                                dim3(256), 0, b->stream, r.S, (uint32_t)Ns[i], r.k0, r.k1);
@@ -1028,8 +1028,8 @@ extern "C" int wolff_server_submit(wolff_server* v, const wolff_job* job, uint64
     uint64_t N = 0;
     int rc = check_params(job->dim, job->L, job->J, job->T, &N);
     if (rc) return rc;
-    if (job->start < -1 || job->start > 1 || job->reserved != 0)
-        return fail(WOLFF_EINVAL, "bad start or reserved field");
+    if (job->start < -1 || job->start > 1 || (job->flags & ~WOLFF_JOB_UPDATE_ONLY) != 0)
+        return fail(WOLFF_EINVAL, "bad start or flags field");
     if (job->n_updates > T_LIMIT) return fail(WOLFF_ERANGE, "too many updates");
     SrvJob j;
     j.spec = *job;
@@ -1078,7 +1078,7 @@ static int server_admit(wolff_server* v)
         r.k1 = (uint32_t)(j.spec.seed >> 32);
         r.t = 0;
         r.n_left = (uint32_t)j.spec.n_updates;
-        r.measure = 1;
+        r.measure = (j.spec.flags & WOLFF_JOB_UPDATE_ONLY) ? 0u : 1u;
         j.fresh = true;
         j.state = WOLFF_JOB_RUNNING;
         v->resident += j.footprint;

@@ -20,7 +20,8 @@ def percentile(xs, q):
 
 
 def run_stream(jobs, quantum_ms: float = 5.0, hbm_budget: int = 0, max_slots: int = 0,
-               max_wall_s: float | None = None, keep_records: bool = False):
+               max_wall_s: float | None = None, keep_records: bool = False,
+               update_only: bool = True, progress=None):
     """Serve `jobs` (objects with dim, L, J, T, seed, n_updates, arrival_s).
 
     Returns a dict with per-job latency, p50/p99, aggregate added spins/s and
@@ -34,12 +35,13 @@ def run_stream(jobs, quantum_ms: float = 5.0, hbm_budget: int = 0, max_slots: in
     i = 0
     submitted = 0
     max_queue = 0
+    last_report = 0.0
     while True:
         now = time.perf_counter() - t0
         while i < len(order) and jobs[order[i]].arrival_s <= now and \
                 (max_wall_s is None or jobs[order[i]].arrival_s <= max_wall_s):
             j = jobs[order[i]]
-            jid = srv.submit(j)
+            jid = srv.submit(j, update_only=update_only)
             arrival[jid] = j.arrival_s
             index_of[jid] = order[i]
             submitted += 1
@@ -56,6 +58,10 @@ def run_stream(jobs, quantum_ms: float = 5.0, hbm_budget: int = 0, max_slots: in
             continue
         srv.step(quantum_ms)
         done_t = time.perf_counter() - t0
+        if progress is not None and done_t - last_report > 5.0:
+            last_report = done_t
+            progress("serve t=%.1f s: submitted %d, finished %d, queued %d, running %d"
+                     % (done_t, submitted, len(latency), st["queued"], st["running"]))
         for jid in srv.finished():
             rec = srv.take(jid)
             latency[jid] = done_t - arrival[jid]
@@ -79,8 +85,14 @@ def run_stream(jobs, quantum_ms: float = 5.0, hbm_budget: int = 0, max_slots: in
     }
 
 
-def capacity(jobs, quantum_ms: float = 5.0, hbm_budget: int = 0) -> float:
-    """Jobs per second when all of `jobs` are waiting at time 0."""
+def capacity(jobs, quantum_ms: float = 5.0, hbm_budget: int = 0, progress=None) -> dict:
+    """Estimate the job rate that keeps every workgroup slot busy.
+
+    All of `jobs` are queued at time 0 (fewer than the slots, so each starts
+    at once and its completion time is its service time); by Little's law a
+    stream keeps `slots` jobs resident at rate slots / mean service time."""
     closed = [type(j)(**{**j.as_dict(), "arrival_s": 0.0}) for j in jobs]
-    r = run_stream(closed, quantum_ms=quantum_ms, hbm_budget=hbm_budget)
-    return r["jobs"] / r["wall_s"]
+    r = run_stream(closed, quantum_ms=quantum_ms, hbm_budget=hbm_budget, progress=progress)
+    service = r["mean_latency_s"]
+    return {"jobs_per_s": r["slots"] / service, "mean_service_s": service,
+            "slots": r["slots"], "closed_batch_jobs_per_s": r["jobs"] / r["wall_s"]}

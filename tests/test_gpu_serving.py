@@ -123,3 +123,18 @@ def test_server_rejects_oversized_job():
         with pytest.raises(binding.WolffError) as e:
             srv.submit(workloads.Job(2, 1024, TC2, 1, 10))
         assert e.value.code == binding.EINVAL
+
+
+def test_server_update_only_jobs():
+    jobs = mixed_jobs(12, seed=3)
+    results = {}
+    with binding.Server() as srv:
+        ids = {srv.submit(j, update_only=True): k for k, j in enumerate(jobs)}
+        while len(results) < len(jobs):
+            srv.step(1.0)
+            for jid in srv.finished():
+                results[ids[jid]] = as_array(srv.take(jid))
+    for k, j in enumerate(jobs):
+        ref, _ = alone(j)
+        assert (results[k][:, 0] == binding.NOT_MEASURED).all()
+        assert (results[k][:, 1:] == ref[:, 1:]).all(), k
