@@ -114,10 +114,17 @@ def plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered=True):
     }
 
 
-def batch_leg(binding, workloads, dim, L, n_rep, warmup, steps, wg=256, q=2048):
+def batch_leg(binding, workloads, dim, L, n_rep, warmup, steps, wg=None, q=None):
     """Batched persistent form: n_rep same-shape replicas at T_c, one launch
-    per run; warmup updates, then `steps` timed updates of every replica."""
+    per run; warmup updates, then `steps` timed updates of every replica.
+    Tile sizes come from the autotuner unless given."""
     jobs = workloads.same_shape_jobs(dim, L, n_rep, warmup + steps)
+    tuned = None
+    if wg is None or q is None:
+        from paper_1110_0899_amd import autotune
+        tjobs = workloads.same_shape_jobs(dim, L, min(n_rep, 128), 16)
+        tuned = autotune.tune(tjobs, warm=8, timed=4, start=1, log=log)
+        wg, q = tuned["wg"], tuned["queue_entries"]
     b = binding.Batch(jobs, start=1)
     b.set_tiles(wg, q)
     b.set_measure(True)
@@ -144,6 +151,8 @@ def batch_leg(binding, workloads, dim, L, n_rep, warmup, steps, wg=256, q=2048):
         "added_per_s": added / wall, "updates_per_s": n_rep * steps / wall,
         "mean_csize": added / (n_rep * steps),
         "kernel_GBs_algorithmic": BYTES_PER_ADDED[dim] * added / kernel_s / 1e9,
+        "kernel_frac_of_hbm_peak": BYTES_PER_ADDED[dim] * added / kernel_s / 1e9 / HBM_PEAK_GBS,
+        "tiles": "autotuner" if tuned else "fixed",
     }
 
 

@@ -130,6 +130,12 @@ int wolff_set_stream(wolff_sim *s, void *hip_stream);
 #define WOLFF_PATH_TEAM   2
 int wolff_set_path(wolff_sim *s, int path, int workgroups);
 
+/* Team path: replay a captured HIP graph of `chunk` updates (the seed,
+ * growth and measurement launches of each) instead of launching them one by
+ * one; 0 launches every kernel directly.  Default 16.  Graphs are not used
+ * while kernel timing (wolff_profile) is on. */
+int wolff_set_graph(wolff_sim *s, int chunk);
+
 /* Kernel timing with HIP events on the handle's stream.  While on, every
  * launch of the cluster-growth kernel and of the measurement kernel is
  * bracketed by events; wolff_profile_read synchronises and returns the summed
@@ -186,6 +192,10 @@ int wolff_batch_progress(wolff_batch *b, int job, uint64_t *left, uint64_t *t);
 int wolff_batch_get_spins(wolff_batch *b, int job, int8_t *host, uint64_t n);
 
 int wolff_batch_set_measure(wolff_batch *b, int on);
+
+/* 1 (default): each wolff_batch_run replays a captured HIP graph of its
+ * launches (one graph per distinct launch configuration); 0: direct launches. */
+int wolff_batch_set_graph(wolff_batch *b, int on);
 int wolff_batch_set_stream(wolff_batch *b, void *hip_stream);
 
 /* Workgroup size / LDS queue of the batched kernel, picked by the tuner:

@@ -1,0 +1,98 @@
+"""Autotuner for the batched kernel's tile sizes (workgroup size, LDS frontier
+ring entries).
+
+Every candidate runs the *same* replicas from the same state for the same
+updates (the random stream does not depend on the tiles, so the work is
+identical and the results bit-equal), and the candidate with the shortest
+kernel time wins.  Results are cached in a JSON file keyed by
+(GPU architecture, dim, log2 of L rounded up, replica count class); the file
+is $WOLFF_TUNE_CACHE or ~/.cache/wolff_mi355x_tune.json.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+from . import binding
+
+CANDIDATES = [(128, 1024), (128, 2048), (256, 1024), (256, 2048), (256, 4096),
+              (512, 2048), (512, 4096)]
+
+
+def cache_path() -> str:
+    return os.environ.get("WOLFF_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "wolff_mi355x_tune.json"))
+
+
+def _arch() -> str:
+    import torch
+    try:
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def key(dim: int, L: int, n_replicas: int) -> str:
+    return "%s|d%d|L2^%d|B2^%d" % (_arch(), dim, math.ceil(math.log2(max(L, 2))),
+                                   math.ceil(math.log2(max(n_replicas, 1))))
+
+
+def _load_cache() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(k: str, v: dict):
+    c = _load_cache()
+    c[k] = v
+    path = cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(c, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def measure(jobs, wg: int, q: int, warm: int, timed: int, start: int) -> float:
+    """Kernel milliseconds of `timed` updates of every replica after `warm`."""
+    with binding.Batch(jobs, start=start) as b:
+        b.set_tiles(wg, q)
+        if warm:
+            b.run(warm)
+            b.last_ms()
+        b.run(timed)
+        return b.last_ms()
+
+
+def tune(jobs, warm: int = 4, timed: int = 4, start: int = 1, candidates=None,
+         use_cache: bool = True, log=None) -> dict:
+    """Best (wg, queue_entries) for a list of same-class jobs."""
+    j0 = jobs[0]
+    k = key(j0.dim, j0.L, len(jobs))
+    if use_cache:
+        hit = _load_cache().get(k)
+        if hit:
+            return hit
+    cands = candidates or CANDIDATES
+    best = None
+    trials = []
+    t0 = time.time()
+    for wg, q in cands:
+        ms = measure(jobs, wg, q, warm, timed, start)
+        trials.append({"wg": wg, "queue_entries": q, "ms": ms})
+        if log:
+            log("tune %s: wg=%d q=%d -> %.1f ms" % (k, wg, q, ms))
+        if best is None or ms < best["ms"]:
+            best = {"wg": wg, "queue_entries": q, "ms": ms}
+    result = {"wg": best["wg"], "queue_entries": best["queue_entries"], "key": k,
+              "trials": trials, "tune_seconds": time.time() - t0}
+    _store(k, result)
+    return result

@@ -81,6 +81,7 @@ SIGNATURES = {
     "wolff_set_measure": (_I, [_P, _I]),
     "wolff_set_stream": (_I, [_P, _P]),
     "wolff_set_path": (_I, [_P, _I, _I]),
+    "wolff_set_graph": (_I, [_P, _I]),
     "wolff_profile": (_I, [_P, _I]),
     "wolff_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_U64),
                                 ctypes.POINTER(_D), ctypes.POINTER(_U64)]),
@@ -94,6 +95,7 @@ SIGNATURES = {
     "wolff_batch_get_spins": (_I, [_P, _I, _P, _U64]),
     "wolff_batch_set_measure": (_I, [_P, _I]),
     "wolff_batch_set_stream": (_I, [_P, _P]),
+    "wolff_batch_set_graph": (_I, [_P, _I]),
     "wolff_batch_set_tiles": (_I, [_P, _I, _I]),
     "wolff_batch_last_ms": (_I, [_P, ctypes.POINTER(_D)]),
     "wolff_server_create": (_I, [_U64, _I, ctypes.POINTER(_P)]),
@@ -211,6 +213,9 @@ class Simulation:
     def set_path(self, path: int, workgroups: int = 0):
         _check(load().wolff_set_path(self._h, path, workgroups), "wolff_set_path")
 
+    def set_graph(self, chunk: int):
+        _check(load().wolff_set_graph(self._h, int(chunk)), "wolff_set_graph")
+
     def profile(self, on: bool):
         _check(load().wolff_profile(self._h, 1 if on else 0), "wolff_profile")
 
@@ -287,6 +292,9 @@ class Batch:
     def set_stream(self, stream=None):
         _check(load().wolff_batch_set_stream(self._h, _stream_handle(stream)),
                "wolff_batch_set_stream")
+
+    def set_graph(self, on: bool):
+        _check(load().wolff_batch_set_graph(self._h, 1 if on else 0), "wolff_batch_set_graph")
 
     def set_tiles(self, wg: int, queue_entries: int):
         _check(load().wolff_batch_set_tiles(self._h, wg, queue_entries), "wolff_batch_set_tiles")

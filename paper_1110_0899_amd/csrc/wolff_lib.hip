@@ -196,6 +196,11 @@ struct wolff_sim {
     int single_wg = 256;
     int single_q = 2048;
 
+    int graph_chunk = 16;                 // updates per captured graph (0 = no graphs)
+    hipGraphExec_t graph = nullptr;       // team-path chunk of graph_chunk updates
+    int graph_key[3] = {-1, -1, -1};      // (chunk, measure, team size) it was captured with
+    hipStream_t graph_stream = nullptr;
+
     bool profiling = false;
     std::vector<EventPair> ev_grow, ev_meas, ev_free;
     double grow_ms = 0.0, meas_ms = 0.0;
@@ -223,6 +228,7 @@ static void free_sim(wolff_sim* s)
             (void)hipEventDestroy(e.a);
             (void)hipEventDestroy(e.b);
         }
+    if (s->graph) (void)hipGraphExecDestroy(s->graph);
     if (s->S) (void)hipFree(s->S);
     if (s->ov) (void)hipFree(s->ov);
     if (s->gq) (void)hipFree(s->gq);
@@ -453,6 +459,43 @@ static int run_team_update(wolff_sim* s)
     return WOLFF_OK;
 }
 
+static int ensure_team_graph(wolff_sim* s)
+{
+    const int key[3] = {s->graph_chunk, s->measure, team_size(s)};
+    if (s->graph && s->graph_stream == s->stream && key[0] == s->graph_key[0] &&
+        key[1] == s->graph_key[1] && key[2] == s->graph_key[2])
+        return WOLFF_OK;
+    if (s->graph) {
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        HIP_TRY(hipGraphExecDestroy(s->graph));
+        s->graph = nullptr;
+    }
+    HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeRelaxed));
+    int rc = WOLFF_OK;
+    for (int u = 0; u < s->graph_chunk && rc == WOLFF_OK; ++u) rc = run_team_update(s);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s->stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    HIP_TRY(e);
+    const hipError_t ei = hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_TRY(ei);
+    s->graph_stream = s->stream;
+    for (int i = 0; i < 3; ++i) s->graph_key[i] = key[i];
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_set_graph(wolff_sim* s, int chunk)
+{
+    if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
+    if (chunk < 0 || chunk > 4096) return fail(WOLFF_EINVAL, "chunk must be in [0, 4096]");
+    s->graph_chunk = chunk;
+    return WOLFF_OK;
+}
+
 extern "C" int wolff_run(wolff_sim* s, uint64_t n)
 {
     if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
@@ -463,7 +506,16 @@ extern "C" int wolff_run(wolff_sim* s, uint64_t n)
     const int path = resolved_path(s);
     if (path == WOLFF_PATH_TEAM) {
         if ((rc = ensure_team_queue(s))) return rc;
-        for (uint64_t u = 0; u < n; ++u)
+        uint64_t u = 0;
+        const uint64_t chunk = (uint64_t)s->graph_chunk;
+        if (!s->profiling && chunk > 0 && n >= chunk) {
+            // the three launches of `chunk` updates, captured once and replayed;
+            // every kernel argument is a device pointer whose contents carry
+            // the state, so one graph serves every later chunk
+            if ((rc = ensure_team_graph(s))) return rc;
+            for (; u + chunk <= n; u += chunk) HIP_TRY(hipGraphLaunch(s->graph, s->stream));
+        }
+        for (; u < n; ++u)
             if ((rc = run_team_update(s))) return rc;
     } else {
         // one workgroup runs the updates; chunk so that one launch stays short
@@ -652,6 +704,9 @@ struct wolff_batch {
     int measure = 1;
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
     bool timed = false;
+    bool use_graph = true;
+    // captured (counter reset + persistent launch), keyed by its launch arguments
+    std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
 };
 
 static void free_batch(wolff_batch* b)
@@ -664,6 +719,7 @@ static void free_batch(wolff_batch* b)
     if (b->d_reps) (void)hipFree(b->d_reps);
     if (b->d_order) (void)hipFree(b->d_order);
     if (b->d_next) (void)hipFree(b->d_next);
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
     if (b->ev_a) (void)hipEventDestroy(b->ev_a);
     if (b->ev_b) (void)hipEventDestroy(b->ev_b);
     if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
@@ -797,6 +853,13 @@ extern "C" int wolff_batch_set_measure(wolff_batch* b, int on)
     return WOLFF_OK;
 }
 
+extern "C" int wolff_batch_set_graph(wolff_batch* b, int on)
+{
+    if (!b) return fail(WOLFF_EINVAL, "batch is NULL");
+    b->use_graph = on != 0;
+    return WOLFF_OK;
+}
+
 extern "C" int wolff_batch_set_stream(wolff_batch* b, void* hip_stream)
 {
     if (!b) return fail(WOLFF_EINVAL, "batch is NULL");
@@ -827,8 +890,30 @@ extern "C" int wolff_batch_run(wolff_batch* b, uint64_t max_updates)
     const uint32_t n = (uint32_t)b->jobs.size();
     const uint32_t grid = (uint32_t)std::min<uint64_t>(n, resident);
     HIP_TRY(hipEventRecord(b->ev_a, b->stream));
-    HIP_TRY(launch_batch(b->wg, grid, (uint32_t)b->qentries, b->stream, b->d_reps, b->d_order, n,
-                         b->d_next, (uint32_t)max_updates));
+    if (b->use_graph) {
+        const std::vector<uint64_t> key = {(uint64_t)b->wg, (uint64_t)b->qentries, grid, max_updates,
+                                           (uint64_t)(uintptr_t)b->stream};
+        auto it = b->graphs.find(key);
+        if (it == b->graphs.end()) {
+            HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+            const hipError_t el = launch_batch(b->wg, grid, (uint32_t)b->qentries, b->stream,
+                                               b->d_reps, b->d_order, n, b->d_next,
+                                               (uint32_t)max_updates);
+            hipGraph_t g = nullptr;
+            const hipError_t ec = hipStreamEndCapture(b->stream, &g);
+            HIP_TRY(el);
+            HIP_TRY(ec);
+            hipGraphExec_t ex = nullptr;
+            const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIP_TRY(ei);
+            it = b->graphs.emplace(key, ex).first;
+        }
+        HIP_TRY(hipGraphLaunch(it->second, b->stream));
+    } else {
+        HIP_TRY(launch_batch(b->wg, grid, (uint32_t)b->qentries, b->stream, b->d_reps, b->d_order,
+                             n, b->d_next, (uint32_t)max_updates));
+    }
     HIP_TRY(hipEventRecord(b->ev_b, b->stream));
     b->timed = true;
     for (size_t i = 0; i < b->jobs.size(); ++i) {

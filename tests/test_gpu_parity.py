@@ -202,3 +202,37 @@ def test_small_lattices_team(dim, L, T, n):
 
 def test_cold_lattice_team():
     check_cold(binding.PATH_TEAM)
+
+
+# ---- captured graphs
+@pytest.mark.parametrize("measure", [True, False])
+def test_team_graph_replays_match_oracle(measure):
+    dim, L, T, seed = 2, 40, TC2, 44
+    ref, Sref = oracle_series(dim, L, T, seed, 120)
+    with binding.Simulation(dim, L, 1.0, T, seed) as sim:
+        sim.set_path(binding.PATH_TEAM, 8)
+        sim.set_measure(measure)
+        sim.set_graph(16)
+        got = []
+        for n in (37, 40, 16, 27):          # replays + eager remainders, synchronised in between
+            sim.run(n)
+            got.append(as_array(sim.observables()))
+            sim.synchronize()
+        got = np.concatenate(got)
+        S = sim.spins()
+    cols = slice(0, 3) if measure else slice(1, 3)
+    assert (got[:, cols] == ref[:, cols]).all()
+    assert (S == Sref).all()
+
+
+def test_batch_graph_replays_match_oracle():
+    jobs = [workloads.Job(2, 24, TC2, 61, 90), workloads.Job(3, 6, T3, 62, 90)]
+    with binding.Batch(jobs) as b:
+        b.set_graph(True)
+        for _ in range(6):                 # the same captured launch replayed 6 times
+            b.run(15)
+            b.progress(0)
+        for i, j in enumerate(jobs):
+            ref, Sref = oracle_series(j.dim, j.L, j.T, j.seed, j.n_updates)
+            assert (as_array(b.records(i)) == ref).all()
+            assert (b.spins(i) == Sref).all()
