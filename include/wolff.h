@@ -130,6 +130,10 @@ int wolff_set_stream(wolff_sim *s, void *hip_stream);
 #define WOLFF_PATH_TEAM   2
 int wolff_set_path(wolff_sim *s, int path, int workgroups);
 
+/* Workgroup size and LDS frontier ring entries of the one-workgroup path
+ * (same ranges as wolff_batch_set_tiles).  Default 256 and 2048. */
+int wolff_set_tiles(wolff_sim *s, int wg, int queue_entries);
+
 /* Team path: replay a captured HIP graph of `chunk` updates (the seed,
  * growth and measurement launches of each) instead of launching them one by
  * one; 0 launches every kernel directly.  Default 16.  Graphs are not used

@@ -82,6 +82,7 @@ SIGNATURES = {
     "wolff_set_stream": (_I, [_P, _P]),
     "wolff_set_path": (_I, [_P, _I, _I]),
     "wolff_set_graph": (_I, [_P, _I]),
+    "wolff_set_tiles": (_I, [_P, _I, _I]),
     "wolff_profile": (_I, [_P, _I]),
     "wolff_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_U64),
                                 ctypes.POINTER(_D), ctypes.POINTER(_U64)]),
@@ -215,6 +216,9 @@ class Simulation:
 
     def set_graph(self, chunk: int):
         _check(load().wolff_set_graph(self._h, int(chunk)), "wolff_set_graph")
+
+    def set_tiles(self, wg: int, queue_entries: int):
+        _check(load().wolff_set_tiles(self._h, int(wg), int(queue_entries)), "wolff_set_tiles")
 
     def profile(self, on: bool):
         _check(load().wolff_profile(self._h, 1 if on else 0), "wolff_profile")

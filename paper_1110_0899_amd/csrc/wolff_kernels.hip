@@ -173,8 +173,10 @@ __device__ __forceinline__ void scalar_counts(const int8_t* S, const Geo& g, uin
 }
 
 // This thread's counts over its share of the lattice: items first, first +
-// stride, ... (chunks when L % 16 == 0, sites otherwise).
-template <int DIM>
+// stride, ... (chunks when L % 16 == 0, sites otherwise).  UNROLL chunks are
+// in flight per thread: 4 in the grid-wide kernel, 1 inside the growth
+// kernel, where the registers of four chunks would halve the resident waves.
+template <int DIM, int UNROLL>
 __device__ __forceinline__ void lattice_counts(const int8_t* S, const Geo& g, uint32_t first,
                                                uint32_t stride, uint64_t& ndiff, uint64_t& nneg)
 {
@@ -182,14 +184,16 @@ __device__ __forceinline__ void lattice_counts(const int8_t* S, const Geo& g, ui
     if ((g.L & 15u) == 0u) {
         const uint32_t nchunks = g.N >> 4;
         uint32_t c = first;
-        for (; c + 3u * stride < nchunks; c += 4u * stride) {        // 4 chunks in flight
-            uint32_t d0, n0, d1, n1, d2, n2, d3, n3;
-            chunk_counts<DIM>(S, g, c, d0, n0);
-            chunk_counts<DIM>(S, g, c + stride, d1, n1);
-            chunk_counts<DIM>(S, g, c + 2u * stride, d2, n2);
-            chunk_counts<DIM>(S, g, c + 3u * stride, d3, n3);
-            d += d0 + d1 + d2 + d3;
-            neg += n0 + n1 + n2 + n3;
+        if (UNROLL == 4) {
+            for (; c + 3u * stride < nchunks; c += 4u * stride) {
+                uint32_t d0, n0, d1, n1, d2, n2, d3, n3;
+                chunk_counts<DIM>(S, g, c, d0, n0);
+                chunk_counts<DIM>(S, g, c + stride, d1, n1);
+                chunk_counts<DIM>(S, g, c + 2u * stride, d2, n2);
+                chunk_counts<DIM>(S, g, c + 3u * stride, d3, n3);
+                d += d0 + d1 + d2 + d3;
+                neg += n0 + n1 + n2 + n3;
+            }
         }
         for (; c < nchunks; c += stride) {
             uint32_t d0, n0;
@@ -216,13 +220,13 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
 
 // (B, M) of one lattice by one workgroup; every thread receives the result.
 template <int WG, int DIM>
-__device__ void reduce_lattice_wg(const int8_t* S, const Geo& g, long long* red,
+__device__ __forceinline__ void reduce_lattice_wg(const int8_t* S, const Geo& g, long long* red,
                                   int64_t& Bout, int64_t& Mout)
 {
     constexpr int NW = WG / WAVE;
     const uint32_t tid = threadIdx.x;
     uint64_t d, neg;
-    lattice_counts<DIM>(S, g, tid, WG, d, neg);
+    lattice_counts<DIM, 1>(S, g, tid, WG, d, neg);
     d = wave_sum_u64(d);
     neg = wave_sum_u64(neg);
     const uint32_t wv = tid / WAVE;
@@ -266,7 +270,7 @@ __device__ __forceinline__ uint32_t budget_spent(const WgCtl* c, uint64_t budget
 }
 
 template <int WG, int DIM>
-__device__ void run_rep(Rep* R, uint32_t max_updates, uint64_t budget, uint32_t qmask,
+__device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t budget, uint32_t qmask,
                         uint32_t* q, uint32_t* wave_cnt, long long* red, WgCtl* ctl)
 {
     constexpr int NW = WG / WAVE;
@@ -382,7 +386,7 @@ __device__ void run_rep(Rep* R, uint32_t max_updates, uint64_t budget, uint32_t 
 // (wall-clock ticks, 0 = none) is exhausted.  A replica is only ever
 // advanced by one workgroup per launch, so its claims are workgroup-scope;
 // the kernel boundary publishes its state to the next launch.
-template <int WG>
+template <int WG, int DIMS>
 __global__ __launch_bounds__(WG) void batch_kernel(Rep* reps, const uint32_t* order,
                                                    uint32_t n_reps, uint32_t* next,
                                                    uint32_t max_updates, uint32_t qmask,
@@ -399,8 +403,11 @@ __global__ __launch_bounds__(WG) void batch_kernel(Rep* reps, const uint32_t* or
     __syncthreads();
     uint32_t idx = blockIdx.x;
     while (idx < n_reps) {
-        Rep* R = reps + order[idx];
-        if (R->dim == 2)
+        // the replica is the same for the whole workgroup: keep its index and
+        // every descriptor field in scalar registers
+        const uint32_t r = __builtin_amdgcn_readfirstlane(order[idx]);
+        Rep* R = reps + r;
+        if (DIMS == 2 || (DIMS == 0 && R->dim == 2))
             run_rep<WG, 2>(R, max_updates, budget, qmask, q, wave_cnt, red, &ctl);
         else
             run_rep<WG, 3>(R, max_updates, budget, qmask, q, wave_cnt, red, &ctl);
@@ -409,7 +416,7 @@ __global__ __launch_bounds__(WG) void batch_kernel(Rep* reps, const uint32_t* or
             ctl.idx = ctl.stop ? n_reps : gridDim.x + atomicAdd(next, 1u);
         }
         __syncthreads();
-        idx = ctl.idx;
+        idx = __builtin_amdgcn_readfirstlane(ctl.idx);
         __syncthreads();
     }
 }
@@ -650,7 +657,7 @@ __global__ __launch_bounds__(256) void measure_grid_kernel(Rep* R, TeamCtl* ctl)
     __shared__ long long red[2 * NW];
     const Geo g = R->geo;
     uint64_t d, neg;
-    lattice_counts<DIM>(R->S, g, blockIdx.x * WG + threadIdx.x, gridDim.x * WG, d, neg);
+    lattice_counts<DIM, 4>(R->S, g, blockIdx.x * WG + threadIdx.x, gridDim.x * WG, d, neg);
     d = wave_sum_u64(d);
     neg = wave_sum_u64(neg);
     if ((threadIdx.x & (WAVE - 1)) == 0) {
@@ -688,11 +695,21 @@ __global__ __launch_bounds__(256) void measure_grid_kernel(Rep* R, TeamCtl* ctl)
 }
 
 // explicit instantiations used by the host code
-template __global__ void batch_kernel<64>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
-template __global__ void batch_kernel<128>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
-template __global__ void batch_kernel<256>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
-template __global__ void batch_kernel<512>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
-template __global__ void batch_kernel<1024>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<64, 0>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<64, 2>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<64, 3>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<128, 0>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<128, 2>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<128, 3>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<256, 0>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<256, 2>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<256, 3>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<512, 0>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<512, 2>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<512, 3>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<1024, 0>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<1024, 2>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+template __global__ void batch_kernel<1024, 3>(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
 template __global__ void measure_rep_kernel<1024>(Rep*);
 template __global__ void team_kernel<256, 2>(Rep*, TeamCtl*, unsigned long long*, uint32_t, uint32_t);
 template __global__ void team_kernel<256, 3>(Rep*, TeamCtl*, unsigned long long*, uint32_t, uint32_t);

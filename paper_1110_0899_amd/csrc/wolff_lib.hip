@@ -126,31 +126,46 @@ static int device_cus()
     return g_num_cus;
 }
 
-static hipError_t launch_batch(int wg, uint32_t grid, uint32_t qentries, hipStream_t st, Rep* reps,
-                               const uint32_t* order, uint32_t n, uint32_t* next, uint32_t max_updates,
-                               uint64_t budget = 0)
+using BatchFn = void (*)(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
+
+// Batched kernel for a workgroup size and a dimension (2, 3, or 0 for a
+// batch that mixes both; the single-dimension variants need fewer registers).
+static BatchFn batch_fn(int wg, int dims)
+{
+#define WOLFF_PICK(W)                                                                   \
+    return dims == 2 ? wolff::batch_kernel<W, 2> : dims == 3 ? wolff::batch_kernel<W, 3> \
+                                                             : wolff::batch_kernel<W, 0>
+    switch (wg) {
+    case 64: WOLFF_PICK(64);
+    case 128: WOLFF_PICK(128);
+    case 512: WOLFF_PICK(512);
+    case 1024: WOLFF_PICK(1024);
+    default: WOLFF_PICK(256);
+    }
+#undef WOLFF_PICK
+}
+
+static hipError_t launch_batch(int wg, int dims, uint32_t grid, uint32_t qentries, hipStream_t st,
+                               Rep* reps, const uint32_t* order, uint32_t n, uint32_t* next,
+                               uint32_t max_updates, uint64_t budget = 0)
 {
     const size_t lds = (size_t)qentries * sizeof(uint32_t);
     const uint32_t qmask = qentries - 1u;
     hipLaunchKernelGGL(wolff::reset_counter_kernel, dim3(1), dim3(64), 0, st, next);
-    switch (wg) {
-    case 64:
-        hipLaunchKernelGGL(wolff::batch_kernel<64>, dim3(grid), dim3(64), lds, st, reps, order, n, next, max_updates, qmask, budget);
-        break;
-    case 128:
-        hipLaunchKernelGGL(wolff::batch_kernel<128>, dim3(grid), dim3(128), lds, st, reps, order, n, next, max_updates, qmask, budget);
-        break;
-    case 512:
-        hipLaunchKernelGGL(wolff::batch_kernel<512>, dim3(grid), dim3(512), lds, st, reps, order, n, next, max_updates, qmask, budget);
-        break;
-    case 1024:
-        hipLaunchKernelGGL(wolff::batch_kernel<1024>, dim3(grid), dim3(1024), lds, st, reps, order, n, next, max_updates, qmask, budget);
-        break;
-    default:
-        hipLaunchKernelGGL(wolff::batch_kernel<256>, dim3(grid), dim3(256), lds, st, reps, order, n, next, max_updates, qmask, budget);
-        break;
-    }
+    hipLaunchKernelGGL(batch_fn(wg, dims), dim3(grid), dim3(wg), lds, st, reps, order, n, next,
+                       max_updates, qmask, budget);
     return hipGetLastError();
+}
+
+// Workgroups of the batched kernel resident at once on the device.
+static int batch_occupancy(int wg, int dims, int qentries)
+{
+    int per_cu = 0;
+    const size_t lds = (size_t)qentries * sizeof(uint32_t);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(batch_fn(wg, dims)), wg, lds);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    return per_cu * device_cus();
 }
 
 static bool valid_tiles(int wg, int q)
@@ -488,6 +503,15 @@ static int ensure_team_graph(wolff_sim* s)
     return WOLFF_OK;
 }
 
+extern "C" int wolff_set_tiles(wolff_sim* s, int wg, int queue_entries)
+{
+    if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
+    if (!valid_tiles(wg, queue_entries)) return fail(WOLFF_EINVAL, "unsupported tile sizes");
+    s->single_wg = wg;
+    s->single_q = queue_entries;
+    return WOLFF_OK;
+}
+
 extern "C" int wolff_set_graph(wolff_sim* s, int chunk)
 {
     if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
@@ -527,7 +551,7 @@ extern "C" int wolff_run(wolff_sim* s, uint64_t n)
                 if ((rc = get_event_pair(s, &ev))) return rc;
                 HIP_TRY(hipEventRecord(ev.a, s->stream));
             }
-            HIP_TRY(launch_batch(s->single_wg, 1, (uint32_t)s->single_q, s->stream, s->d_rep,
+            HIP_TRY(launch_batch(s->single_wg, s->dim, 1, (uint32_t)s->single_q, s->stream, s->d_rep,
                                  s->d_order, 1, s->d_next, m));
             if (s->profiling) {
                 HIP_TRY(hipEventRecord(ev.b, s->stream));
@@ -701,6 +725,7 @@ struct wolff_batch {
     std::vector<uint32_t> order;    // longest expected work first
     int wg = 256;
     int qentries = 2048;
+    int dims = 0;                   // 2 or 3 if every replica has that dimension, else 0
     int measure = 1;
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
     bool timed = false;
@@ -766,6 +791,9 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
         rec_total += std::max<uint64_t>(jobs[i].n_updates, 1);
     }
     b->jobs.assign(jobs, jobs + n_jobs);
+    b->dims = jobs[0].dim;
+    for (int i = 1; i < n_jobs; ++i)
+        if (jobs[i].dim != b->dims) b->dims = 0;
     BATCH_TRY(hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking));
     b->stream = b->own_stream;
     BATCH_TRY(hipMalloc(&b->S, s_total));
@@ -875,28 +903,17 @@ extern "C" int wolff_batch_run(wolff_batch* b, uint64_t max_updates)
     uint32_t active = 0;
     for (size_t i = 0; i < b->jobs.size(); ++i) active += b->left[i] > 0;
     if (active == 0) return WOLFF_OK;
-    int per_cu = 0;
-    const size_t lds = (size_t)b->qentries * sizeof(uint32_t);
-    hipError_t e;
-    switch (b->wg) {
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<64>, 64, lds); break;
-    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<128>, 128, lds); break;
-    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<512>, 512, lds); break;
-    case 1024: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<1024>, 1024, lds); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<256>, 256, lds); break;
-    }
-    HIP_TRY(e);
-    const uint64_t resident = (uint64_t)std::max(per_cu, 1) * (uint64_t)device_cus();
+    const uint64_t resident = (uint64_t)batch_occupancy(b->wg, b->dims, b->qentries);
     const uint32_t n = (uint32_t)b->jobs.size();
     const uint32_t grid = (uint32_t)std::min<uint64_t>(n, resident);
     HIP_TRY(hipEventRecord(b->ev_a, b->stream));
     if (b->use_graph) {
-        const std::vector<uint64_t> key = {(uint64_t)b->wg, (uint64_t)b->qentries, grid, max_updates,
+        const std::vector<uint64_t> key = {(uint64_t)b->wg, (uint64_t)b->dims, (uint64_t)b->qentries, grid, max_updates,
                                            (uint64_t)(uintptr_t)b->stream};
         auto it = b->graphs.find(key);
         if (it == b->graphs.end()) {
             HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
-            const hipError_t el = launch_batch(b->wg, grid, (uint32_t)b->qentries, b->stream,
+            const hipError_t el = launch_batch(b->wg, b->dims, grid, (uint32_t)b->qentries, b->stream,
                                                b->d_reps, b->d_order, n, b->d_next,
                                                (uint32_t)max_updates);
             hipGraph_t g = nullptr;
@@ -911,7 +928,7 @@ extern "C" int wolff_batch_run(wolff_batch* b, uint64_t max_updates)
         }
         HIP_TRY(hipGraphLaunch(it->second, b->stream));
     } else {
-        HIP_TRY(launch_batch(b->wg, grid, (uint32_t)b->qentries, b->stream, b->d_reps, b->d_order,
+        HIP_TRY(launch_batch(b->wg, b->dims, grid, (uint32_t)b->qentries, b->stream, b->d_reps, b->d_order,
                              n, b->d_next, (uint32_t)max_updates));
     }
     HIP_TRY(hipEventRecord(b->ev_b, b->stream));
@@ -1000,22 +1017,6 @@ uint64_t job_footprint(uint64_t N, uint64_t n_updates)
            std::max<uint64_t>(n_updates, 1) * sizeof(wolff_record) + 256;
 }
 
-int batch_occupancy(int wg, int qentries)
-{
-    int per_cu = 0;
-    const size_t lds = (size_t)qentries * sizeof(uint32_t);
-    hipError_t e;
-    switch (wg) {
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<64>, 64, lds); break;
-    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<128>, 128, lds); break;
-    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<512>, 512, lds); break;
-    case 1024: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<1024>, 1024, lds); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wolff::batch_kernel<256>, 256, lds); break;
-    }
-    if (e != hipSuccess || per_cu < 1) per_cu = 1;
-    return per_cu * device_cus();
-}
-
 }  // namespace
 
 struct wolff_server {
@@ -1079,7 +1080,7 @@ extern "C" int wolff_server_create(uint64_t hbm_budget_bytes, int max_slots, wol
         hbm_budget_bytes = (uint64_t)(0.8 * (double)free_b);
     }
     v->budget = hbm_budget_bytes;
-    const int cap = batch_occupancy(v->wg, v->qentries);
+    const int cap = batch_occupancy(v->wg, 0, v->qentries);
     v->slots = (max_slots > 0) ? (uint64_t)std::min(max_slots, cap) : (uint64_t)cap;
     int dev = 0, khz = 0;
     SRV_TRY(hipGetDevice(&dev));
@@ -1194,7 +1195,7 @@ extern "C" int wolff_server_step(wolff_server* v, double quantum_ms, uint64_t* n
         }
         const uint64_t budget = (uint64_t)(quantum_ms * (double)v->ticks_per_ms);
         HIP_TRY(hipEventRecord(v->ev_a, v->stream));
-        HIP_TRY(launch_batch(v->wg, n, (uint32_t)v->qentries, v->stream, v->d_reps, v->d_order, n,
+        HIP_TRY(launch_batch(v->wg, 0, n, (uint32_t)v->qentries, v->stream, v->d_reps, v->d_order, n,
                              v->d_next, 0u, budget == 0 ? 1 : budget));
         HIP_TRY(hipEventRecord(v->ev_b, v->stream));
         HIP_TRY(hipMemcpyAsync(v->h_reps, v->d_reps, n * sizeof(Rep), hipMemcpyDeviceToHost, v->stream));
