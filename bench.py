@@ -223,10 +223,10 @@ def profile_only(args, binding, workloads):
         r = plain_leg(binding, 3, 256, workloads.T_3D, 3, args.warmup, args.steps)
     elif leg == "batch2d":
         r = batch_leg(binding, workloads, 2, 4096, args.batch_replicas, args.warmup,
-                      args.batch_steps)
+                      args.batch_steps, wg=256, q=2048)
     elif leg == "batch3d":
         r = batch_leg(binding, workloads, 3, 256, args.batch_replicas, args.warmup,
-                      args.batch_steps)
+                      args.batch_steps, wg=256, q=2048)
     else:
         raise SystemExit("unknown leg %s" % leg)
     r = {k: v for k, v in r.items() if k not in ("records", "checkpoint")}

@@ -52,18 +52,15 @@ __device__ __forceinline__ uint32_t seed_site(uint32_t k0, uint32_t k1, uint32_t
 }
 
 // ---------------------------------------------------------------- geometry
-// Periodic L^d lattice, site j = x + L*y (+ L*L*z), N < 2^32.
-// Division by L uses a shift when L is a power of two and otherwise the
-// multiply-high by M = floor(2^64 / L) + 1, exact for every j < 2^32.
-struct Geo {
-    uint32_t L;
-    uint32_t N;
-    uint32_t LL;        // L*L (3D); equals N in 2D
-    uint32_t shift;     // log2(L) if L is a power of two, else 0xFFFFFFFF
+// Exact division of a 32-bit numerator by a constant d >= 1: a shift when d
+// is a power of two, otherwise the multiply-high by M = floor(2^64 / d) + 1
+// (exact for every numerator < 2^32 because d < 2^32).
+struct Div {
+    uint32_t shift;     // log2(d) if d is a power of two, else 0xFFFFFFFF
     uint32_t magic_hi;  // M >> 32
     uint32_t magic_lo;  // M & 0xFFFFFFFF
 
-    __device__ __forceinline__ uint32_t div_L(uint32_t j) const
+    __device__ __forceinline__ uint32_t div(uint32_t j) const
     {
         if (shift != 0xFFFFFFFFu) return j >> shift;
         const uint64_t a = (uint64_t)j * magic_hi + (((uint64_t)j * magic_lo) >> 32);
@@ -71,27 +68,105 @@ struct Geo {
     }
 };
 
-// Neighbours of j in slot order (+x, -x, +y, -y[, +z, -z]).
+// Periodic L^d lattice.  Sites are *named* by the logical index
+// j = x + L*y (+ L*L*z) everywhere the method needs a name (the frontier
+// queues, the random-stream counters, the records); spins are *stored*
+// either in that order or, when L is a multiple of 16, in tiles of 128
+// sites (16 x 8 in 2D, 16 x 4 x 2 in 3D) that each fill one 128-byte L2
+// line, so that a site and most of its neighbours share a line:
+//   2D: addr = ((y>>3)*ntx + (x>>4))*128 + (y&7)*16 + (x&15)
+//   3D: addr = (((z>>1)*nty + (y>>2))*ntx + (x>>4))*128 + (z&1)*64 + (y&3)*16 + (x&15)
+// with ntx = L/16 tiles along x and nty = L/TY tiles along y.
+struct Geo {
+    uint32_t L;
+    uint32_t N;
+    uint32_t LL;        // L*L (3D); equals N in 2D
+    uint32_t tiled;     // 1: tiled storage
+    uint32_t ntx;       // tiles along x (tiled storage)
+    uint32_t nty;       // tiles along y (tiled storage)
+    uint32_t ntz;       // tiles along z (tiled storage, 3D)
+    uint32_t pad;
+    Div dL;             // division by L
+    Div dntx;           // division by ntx
+    Div dnty;           // division by nty
+
+    __device__ __forceinline__ uint32_t div_L(uint32_t j) const { return dL.div(j); }
+
+    template <int DIM>
+    __device__ __forceinline__ uint32_t tile_addr(uint32_t x, uint32_t y, uint32_t z) const
+    {
+        if (DIM == 2)
+            return ((((y >> 3) * ntx + (x >> 4)) << 7) | ((y & 7u) << 4) | (x & 15u));
+        return (((((z >> 1) * nty + (y >> 2)) * ntx + (x >> 4)) << 7) | ((z & 1u) << 6) |
+                ((y & 3u) << 4) | (x & 15u));
+    }
+};
+
+// Storage address of site j.
 template <int DIM>
-__device__ __forceinline__ void neighbours(const Geo& g, uint32_t j, uint32_t nb[2 * DIM])
+__device__ __forceinline__ uint32_t site_addr(const Geo& g, uint32_t j)
+{
+    if (!g.tiled) return j;
+    const uint32_t q = g.div_L(j);
+    const uint32_t x = j - q * g.L;
+    if (DIM == 2) return g.tile_addr<2>(x, q, 0u);
+    const uint32_t r = g.div_L(q);
+    return g.tile_addr<3>(x, q - r * g.L, r);
+}
+
+// Neighbours of j in slot order (+x, -x, +y, -y[, +z, -z]): logical indices
+// nb[] and storage addresses sa[].
+template <int DIM>
+__device__ __forceinline__ void neighbours(const Geo& g, uint32_t j, uint32_t nb[2 * DIM],
+                                           uint32_t sa[2 * DIM])
 {
     const uint32_t L = g.L;
     const uint32_t q = g.div_L(j);
     const uint32_t x = j - q * L;
-    nb[0] = (x + 1u == L) ? j + 1u - L : j + 1u;
-    nb[1] = (x == 0u) ? j + L - 1u : j - 1u;
+    const uint32_t xp = (x + 1u == L) ? 0u : x + 1u;
+    const uint32_t xm = (x == 0u) ? L - 1u : x - 1u;
+    nb[0] = j - x + xp;
+    nb[1] = j - x + xm;
     if (DIM == 2) {
         const uint32_t N = g.N;
+        const uint32_t y = q;
         nb[2] = (j >= N - L) ? j - (N - L) : j + L;
         nb[3] = (j >= L) ? j - L : j + (N - L);
+        if (g.tiled) {
+            const uint32_t yp = (y + 1u == L) ? 0u : y + 1u;
+            const uint32_t ym = (y == 0u) ? L - 1u : y - 1u;
+            sa[0] = g.tile_addr<2>(xp, y, 0u);
+            sa[1] = g.tile_addr<2>(xm, y, 0u);
+            sa[2] = g.tile_addr<2>(x, yp, 0u);
+            sa[3] = g.tile_addr<2>(x, ym, 0u);
+        } else {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) sa[m] = nb[m];
+        }
     } else {
         const uint32_t r = g.div_L(q);
         const uint32_t y = q - r * L;
+        const uint32_t z = r;
         const uint32_t LL = g.LL, N = g.N;
         nb[2] = (y + 1u == L) ? j + L - LL : j + L;
         nb[3] = (y == 0u) ? j + LL - L : j - L;
         nb[4] = (j >= N - LL) ? j - (N - LL) : j + LL;
         nb[5] = (j >= LL) ? j - LL : j + (N - LL);
+        if (g.tiled) {
+            const uint32_t yp = (y + 1u == L) ? 0u : y + 1u;
+            const uint32_t ym = (y == 0u) ? L - 1u : y - 1u;
+            const uint32_t zp = (z + 1u == L) ? 0u : z + 1u;
+            const uint32_t zm = (z == 0u) ? L - 1u : z - 1u;
+            sa[0] = g.tile_addr<3>(xp, y, z);
+            sa[1] = g.tile_addr<3>(xm, y, z);
+            sa[2] = g.tile_addr<3>(x, yp, z);
+            sa[3] = g.tile_addr<3>(x, ym, z);
+            sa[4] = g.tile_addr<3>(x, y, zp);
+            sa[5] = g.tile_addr<3>(x, y, zm);
+        } else {
+#pragma unroll
+            for (int m = 0; m < 6; ++m) sa[m] = nb[m];
+        }
     }
 }
 

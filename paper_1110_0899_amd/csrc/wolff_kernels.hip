@@ -32,10 +32,11 @@ __device__ __forceinline__ void expand_site(bool active, uint32_t j, const Geo& 
                                             bool won[2 * DIM])
 {
     if (!active) j = 0u;
-    neighbours<DIM>(g, j, nb);
+    uint32_t sa[2 * DIM];
+    neighbours<DIM>(g, j, nb, sa);
     bool el[2 * DIM];
 #pragma unroll
-    for (int m = 0; m < 2 * DIM; ++m) el[m] = active && (int)S[nb[m]] == s0;
+    for (int m = 0; m < 2 * DIM; ++m) el[m] = active && (int)S[sa[m]] == s0;
 
     uint32_t rp[3] = {0u, 0u, 0u};
     const bool need_plus = el[0] || el[2] || (DIM == 3 && el[2 * (DIM - 1)]);
@@ -58,7 +59,7 @@ __device__ __forceinline__ void expand_site(bool active, uint32_t j, const Geo& 
         act[2 * mu + 1] = a;
     }
 #pragma unroll
-    for (int m = 0; m < 2 * DIM; ++m) won[m] = act[m] && claim<SCOPE>(S, nb[m], s0);
+    for (int m = 0; m < 2 * DIM; ++m) won[m] = act[m] && claim<SCOPE>(S, sa[m], s0);
 }
 
 // Wave-level compaction of the claimed sites: one ballot per neighbour slot,
@@ -129,6 +130,68 @@ __device__ __forceinline__ void chunk_counts(const int8_t* S, const Geo& g, uint
     nneg = __popc(a.x & K) + __popc(a.y & K) + __popc(a.z & K) + __popc(a.w & K);
 }
 
+// Tiled storage: chunk c is row (c & 7) of tile c >> 3, 16 sites along x.
+// The +x neighbours are the row shifted by one byte plus the first byte of
+// the same row of the next tile along x; +y / +z neighbours are the next row
+// of the tile or the matching row of the next tile (periodic).
+template <int DIM>
+__device__ __forceinline__ void chunk_counts_tiled(const int8_t* S, const Geo& g, uint32_t c,
+                                                   uint32_t& ndiff, uint32_t& nneg)
+{
+    const uint4* S4 = reinterpret_cast<const uint4*>(S);
+    const uint32_t* S1 = reinterpret_cast<const uint32_t*>(S);
+    const uint32_t T = c >> 3, row = c & 7u;
+    const uint32_t q1 = g.dntx.div(T);
+    const uint32_t tx = T - q1 * g.ntx;
+    const uint32_t Tx = (tx + 1u == g.ntx) ? T - tx : T + 1u;
+    const uint4 a = S4[c];
+    const uint32_t w4 = S1[((Tx << 3) | row) << 2];
+    const uint32_t K = 0x02020202u;
+    const uint32_t s0 = (a.x >> 8) | (a.y << 24);
+    const uint32_t s1 = (a.y >> 8) | (a.z << 24);
+    const uint32_t s2 = (a.z >> 8) | (a.w << 24);
+    const uint32_t s3 = (a.w >> 8) | (w4 << 24);
+    uint32_t d = __popc((a.x ^ s0) & K) + __popc((a.y ^ s1) & K) + __popc((a.z ^ s2) & K) +
+                 __popc((a.w ^ s3) & K);
+    uint32_t cy;
+    if (DIM == 2) {
+        const uint32_t ty = q1;
+        if (row < 7u) {
+            cy = c + 1u;
+        } else {
+            const uint32_t Ty = (ty + 1u == g.nty) ? tx : T + g.ntx;
+            cy = Ty << 3;
+        }
+    } else {
+        const uint32_t q2 = g.dnty.div(q1);
+        const uint32_t ty = q1 - q2 * g.nty;
+        const uint32_t tz = q2;
+        const uint32_t oy = row & 3u, oz = row >> 2;
+        if (oy < 3u) {
+            cy = c + 1u;
+        } else {
+            const uint32_t Ty = (ty + 1u == g.nty) ? T - ty * g.ntx : T + g.ntx;
+            cy = (Ty << 3) | (oz << 2);
+        }
+        uint32_t cz;
+        if (oz == 0u) {
+            cz = c + 4u;
+        } else {
+            const uint32_t plane = g.ntx * g.nty;
+            const uint32_t Tz = (tz + 1u == g.ntz) ? T - tz * plane : T + plane;
+            cz = (Tz << 3) | oy;
+        }
+        const uint4 z = S4[cz];
+        d += __popc((a.x ^ z.x) & K) + __popc((a.y ^ z.y) & K) + __popc((a.z ^ z.z) & K) +
+             __popc((a.w ^ z.w) & K);
+    }
+    const uint4 b = S4[cy];
+    d += __popc((a.x ^ b.x) & K) + __popc((a.y ^ b.y) & K) + __popc((a.z ^ b.z) & K) +
+         __popc((a.w ^ b.w) & K);
+    ndiff = d;
+    nneg = __popc(a.x & K) + __popc(a.y & K) + __popc(a.z & K) + __popc(a.w & K);
+}
+
 // Scalar form for any L: per site, with coordinates advanced incrementally
 // along the thread's stride (no division in the loop).  Accumulates the same
 // two counts as the vector form.
@@ -181,7 +244,27 @@ __device__ __forceinline__ void lattice_counts(const int8_t* S, const Geo& g, ui
                                                uint32_t stride, uint64_t& ndiff, uint64_t& nneg)
 {
     uint64_t d = 0u, neg = 0u;
-    if ((g.L & 15u) == 0u) {
+    if (g.tiled) {
+        const uint32_t nchunks = g.N >> 4;
+        uint32_t c = first;
+        if (UNROLL == 4) {
+            for (; c + 3u * stride < nchunks; c += 4u * stride) {
+                uint32_t d0, n0, d1, n1, d2, n2, d3, n3;
+                chunk_counts_tiled<DIM>(S, g, c, d0, n0);
+                chunk_counts_tiled<DIM>(S, g, c + stride, d1, n1);
+                chunk_counts_tiled<DIM>(S, g, c + 2u * stride, d2, n2);
+                chunk_counts_tiled<DIM>(S, g, c + 3u * stride, d3, n3);
+                d += d0 + d1 + d2 + d3;
+                neg += n0 + n1 + n2 + n3;
+            }
+        }
+        for (; c < nchunks; c += stride) {
+            uint32_t d0, n0;
+            chunk_counts_tiled<DIM>(S, g, c, d0, n0);
+            d += d0;
+            neg += n0;
+        }
+    } else if ((g.L & 15u) == 0u) {
         const uint32_t nchunks = g.N >> 4;
         uint32_t c = first;
         if (UNROLL == 4) {
@@ -297,8 +380,9 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
         const uint32_t t = t0 + u;
         const uint32_t s = seed_site(k0, k1, t, g.N);             // step (i)
         if (tid == 0) {
-            const int s0 = S[s];
-            claim<SCOPE_WG>(S, s, s0);
+            const uint32_t a = site_addr<DIM>(g, s);
+            const int s0 = S[a];
+            claim<SCOPE_WG>(S, a, s0);
             q[0] = s;
             ctl->s0 = s0;
         }
@@ -426,13 +510,15 @@ __global__ void reset_counter_kernel(uint32_t* c)
     if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0u;
 }
 
-// Initial state: iid +-1 from the domain-2 stream.
-__global__ void init_kernel(int8_t* S, uint32_t N, uint32_t k0, uint32_t k1)
+// Initial state: iid +-1 from the domain-2 stream (site i named logically,
+// stored at its address).
+__global__ void init_kernel(int8_t* S, Geo g, int dim, uint32_t k0, uint32_t k1)
 {
     const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += stride) {
         const U4 r = philox(i, 0u, 0u, DOMAIN_INIT, k0, k1);
-        S[i] = (r.x < 0x80000000u) ? (int8_t)1 : (int8_t)-1;
+        const uint32_t a = (dim == 2) ? site_addr<2>(g, i) : site_addr<3>(g, i);
+        S[a] = (r.x < 0x80000000u) ? (int8_t)1 : (int8_t)-1;
     }
 }
 
@@ -472,8 +558,9 @@ __global__ void team_seed_kernel(Rep* R, TeamCtl* ctl, unsigned long long* gq)
     const uint32_t t = R->t;
     const uint32_t s = seed_site(R->k0, R->k1, t, g.N);
     int8_t* S = R->S;
-    const int s0 = S[s];
-    claim<SCOPE_AGENT>(S, s, s0);
+    const uint32_t a = (R->dim == 2) ? site_addr<2>(g, s) : site_addr<3>(g, s);
+    const int s0 = S[a];
+    claim<SCOPE_AGENT>(S, a, s0);
     uint32_t epoch = ctl->epoch + 1u;
     if (epoch == 0u) epoch = 1u;
     ctl->epoch = epoch;

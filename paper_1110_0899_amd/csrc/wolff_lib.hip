@@ -72,24 +72,78 @@ static uint32_t bond_threshold(double J, double T)
     return (uint32_t)std::floor(scaled);
 }
 
+static wolff::Div make_div(uint32_t d)
+{
+    wolff::Div v;
+    if ((d & (d - 1u)) == 0u) {
+        uint32_t sh = 0;
+        while ((1u << sh) < d) ++sh;
+        v.shift = sh;
+        v.magic_hi = v.magic_lo = 0u;
+    } else {
+        v.shift = 0xFFFFFFFFu;
+        const uint64_t M = UINT64_MAX / d + 1u;     // floor(2^64 / d) + 1
+        v.magic_hi = (uint32_t)(M >> 32);
+        v.magic_lo = (uint32_t)M;
+    }
+    return v;
+}
+
+// Geometry; storage is tiled (128-site tiles) when L is a multiple of 16.
 static Geo make_geo(int dim, uint32_t L)
 {
-    Geo g;
+    Geo g{};
     g.L = L;
     g.LL = L * L;
     g.N = (dim == 2) ? g.LL : g.LL * L;
-    if ((L & (L - 1u)) == 0u) {
-        uint32_t sh = 0;
-        while ((1u << sh) < L) ++sh;
-        g.shift = sh;
-        g.magic_hi = g.magic_lo = 0u;
+    g.dL = make_div(L);
+    g.tiled = (L % 16u == 0u) ? 1u : 0u;
+    if (g.tiled) {
+        g.ntx = L / 16u;
+        g.nty = (dim == 2) ? L / 8u : L / 4u;
+        g.ntz = (dim == 2) ? 1u : L / 2u;
     } else {
-        g.shift = 0xFFFFFFFFu;
-        const uint64_t M = UINT64_MAX / L + 1u;     // floor(2^64 / L) + 1
-        g.magic_hi = (uint32_t)(M >> 32);
-        g.magic_lo = (uint32_t)M;
+        g.ntx = g.nty = g.ntz = 1u;
     }
+    g.dntx = make_div(g.ntx);
+    g.dnty = make_div(g.nty);
     return g;
+}
+
+// Storage address of logical site i (host copy of the device mapping).
+static uint64_t host_site_addr(const Geo& g, int dim, uint64_t i)
+{
+    if (!g.tiled) return i;
+    const uint64_t L = g.L;
+    const uint64_t x = i % L, y = (i / L) % L, z = i / (L * L);
+    if (dim == 2) return ((((y >> 3) * g.ntx + (x >> 4)) << 7) | ((y & 7u) << 4) | (x & 15u));
+    return (((((z >> 1) * g.nty + (y >> 2)) * g.ntx + (x >> 4)) << 7) | ((z & 1u) << 6) |
+            ((y & 3u) << 4) | (x & 15u));
+}
+
+// Device spins (storage order) -> host spins (site order), and back.
+static int copy_spins_out(const Geo& g, int dim, const int8_t* dev, int8_t* host, uint64_t n)
+{
+    if (!g.tiled) {
+        HIP_TRY(hipMemcpy(host, dev, n, hipMemcpyDeviceToHost));
+        return WOLFF_OK;
+    }
+    std::vector<int8_t> tmp(n);
+    HIP_TRY(hipMemcpy(tmp.data(), dev, n, hipMemcpyDeviceToHost));
+    for (uint64_t i = 0; i < n; ++i) host[i] = tmp[host_site_addr(g, dim, i)];
+    return WOLFF_OK;
+}
+
+static int copy_spins_in(const Geo& g, int dim, const int8_t* host, int8_t* dev, uint64_t n)
+{
+    if (!g.tiled) {
+        HIP_TRY(hipMemcpy(dev, host, n, hipMemcpyHostToDevice));
+        return WOLFF_OK;
+    }
+    std::vector<int8_t> tmp(n);
+    for (uint64_t i = 0; i < n; ++i) tmp[host_site_addr(g, dim, i)] = host[i];
+    HIP_TRY(hipMemcpy(dev, tmp.data(), n, hipMemcpyHostToDevice));
+    return WOLFF_OK;
 }
 
 static int check_params(int dim, int L, double J, double T, uint64_t* N)
@@ -354,7 +408,7 @@ extern "C" int wolff_create(int dim, int L, double J, double T, uint64_t seed, w
     CREATE_TRY(hipMalloc(&s->d_rec, s->rec_cap * sizeof(wolff_record)));
 
     hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((N + 255) / 256, 65536)),
-                       dim3(256), 0, s->stream, s->S, (uint32_t)N, (uint32_t)seed,
+                       dim3(256), 0, s->stream, s->S, s->geo, dim, (uint32_t)seed,
                        (uint32_t)(seed >> 32));
     CREATE_TRY(hipGetLastError());
 
@@ -628,8 +682,7 @@ extern "C" int wolff_get_spins(wolff_sim* s, int8_t* host, uint64_t n)
     if (!s || !host) return fail(WOLFF_EINVAL, "NULL argument");
     if (n != s->N) return fail(WOLFF_EINVAL, "n must equal the number of sites");
     HIP_TRY(hipStreamSynchronize(s->stream));
-    HIP_TRY(hipMemcpy(host, s->S, n, hipMemcpyDeviceToHost));
-    return WOLFF_OK;
+    return copy_spins_out(s->geo, s->dim, s->S, host, n);
 }
 
 extern "C" int wolff_set_spins(wolff_sim* s, const int8_t* host, uint64_t n, uint64_t t)
@@ -642,7 +695,7 @@ extern "C" int wolff_set_spins(wolff_sim* s, const int8_t* host, uint64_t n, uin
     Rep r;
     int rc = pull_rep(s, &r);
     if (rc) return rc;
-    HIP_TRY(hipMemcpy(s->S, host, n, hipMemcpyHostToDevice));
+    if ((rc = copy_spins_in(s->geo, s->dim, host, s->S, n))) return rc;
     r.t = (uint32_t)t;
     r.rec_count = 0;
     r.err = 0;
@@ -824,7 +877,7 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
         r.measure = (j.flags & WOLFF_JOB_UPDATE_ONLY) ? 0u : 1u;
         if (j.start == 0) {
             hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((Ns[i] + 255) / 256, 65536)),
-                               dim3(256), 0, b->stream, r.S, (uint32_t)Ns[i], r.k0, r.k1);
+                               dim3(256), 0, b->stream, r.S, r.geo, j.dim, r.k0, r.k1);
             BATCH_TRY(hipGetLastError());
         } else {
             BATCH_TRY(hipMemsetAsync(r.S, j.start > 0 ? 0x01 : 0xFF, Ns[i], b->stream));
@@ -988,8 +1041,7 @@ extern "C" int wolff_batch_get_spins(wolff_batch* b, int job, int8_t* host, uint
     const Rep& r = b->reps[job];
     if (n != r.geo.N) return fail(WOLFF_EINVAL, "n must equal the number of sites");
     HIP_TRY(hipStreamSynchronize(b->stream));
-    HIP_TRY(hipMemcpy(host, r.S, n, hipMemcpyDeviceToHost));
-    return WOLFF_OK;
+    return copy_spins_out(r.geo, r.dim, r.S, host, n);
 }
 
 // ================================================================== server
@@ -1145,8 +1197,8 @@ static int server_admit(wolff_server* v)
         HIP_TRY(hipMemsetAsync(S, 0, padded_bytes(j.N), v->stream));
         if (j.spec.start == 0) {
             hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((j.N + 255) / 256, 65536)),
-                               dim3(256), 0, v->stream, S, (uint32_t)j.N, (uint32_t)j.spec.seed,
-                               (uint32_t)(j.spec.seed >> 32));
+                               dim3(256), 0, v->stream, S, make_geo(j.spec.dim, (uint32_t)j.spec.L),
+                               j.spec.dim, (uint32_t)j.spec.seed, (uint32_t)(j.spec.seed >> 32));
             HIP_TRY(hipGetLastError());
         } else {
             HIP_TRY(hipMemsetAsync(S, j.spec.start > 0 ? 0x01 : 0xFF, j.N, v->stream));

@@ -74,6 +74,8 @@ def test_c1_full_run_single_path():
 SMALL_CASES = [
     (2, 2, 2.0, 300), (2, 3, TC2, 300), (2, 17, 1.8, 300), (2, 64, TC2, 300), (2, 100, 2.6, 200),
     (3, 2, T3, 300), (3, 3, 4.0, 300), (3, 8, T3, 300), (3, 13, 4.7, 200), (3, 32, T3, 100),
+    # tiled storage (L a multiple of 16), incl. tile counts that are not powers of two
+    (2, 16, 2.0, 300), (2, 48, 2.2, 200), (3, 16, 4.0, 200), (3, 48, T3, 60),
 ]
 
 
