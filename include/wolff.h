@@ -203,7 +203,8 @@ int wolff_batch_set_graph(wolff_batch *b, int on);
 int wolff_batch_set_stream(wolff_batch *b, void *hip_stream);
 
 /* Workgroup size / LDS queue of the batched kernel, picked by the tuner:
- * wg in {64, 128, 256, 512, 1024}, queue entries a power of two >= wg. */
+ * wg in {64, 128, 256, 512, 1024}, queue entries a power of two in
+ * [wg, 8192]. */
 int wolff_batch_set_tiles(wolff_batch *b, int wg, int queue_entries);
 
 /* Elapsed milliseconds of the last wolff_batch_run's kernel (HIP events on

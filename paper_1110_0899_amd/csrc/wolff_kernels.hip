@@ -25,11 +25,46 @@ constexpr int SCOPE_AGENT = __HIP_MEMORY_SCOPE_AGENT;
 // One Philox block serves all +mu bonds of j.  Random words are only drawn
 // for eligible neighbours; the cluster does not depend on which thread
 // claims a site first, so no ordering between threads is needed.
-template <int DIM, int SCOPE>
+// Claim table of the one-workgroup path.  Only one workgroup touches the
+// lattice during a launch, so the only races on a site are between threads
+// of the same step: they are settled in an LDS hash table keyed by storage
+// address (CAS on an empty slot), and the winner flips the spin with a plain
+// byte store, visible to the next step after the step's barrier.  A probe
+// sequence longer than TAB_PROBES falls back to the atomic claim on the spin
+// word; the fallback is consistent because slots only fill during a step, so
+// every thread probing a given site either finds its entry or finds the same
+// full window.  The workgroup empties the whole table after each step.
+constexpr uint32_t TAB_EMPTY = 0xFFFFFFFFu;
+constexpr uint32_t TAB_PROBES = 32u;
+
+// Table entries for a workgroup size: 8 per thread (a step claims at most
+// 2d per thread, and usually far fewer).
+__host__ __device__ constexpr uint32_t tab_entries(int wg) { return 8u * (uint32_t)wg; }
+__host__ __device__ constexpr uint32_t tab_shift(int wg)
+{
+    return wg == 64 ? 23u : wg == 128 ? 22u : wg == 256 ? 21u : wg == 512 ? 20u : 19u;
+}
+
+// 1: won through the table; 0: another thread holds the site;
+// 2: no free slot within the probe window (use the atomic claim).
+template <int WG>
+__device__ __forceinline__ int table_claim(uint32_t* tab, uint32_t a)
+{
+    uint32_t h = (a * 0x9E3779B1u) >> tab_shift(WG);
+    for (uint32_t p = 0; p < TAB_PROBES; ++p) {
+        const uint32_t prev = atomicCAS(&tab[h], TAB_EMPTY, a);
+        if (prev == TAB_EMPTY) return 1;
+        if (prev == a) return 0;
+        h = (h + 1u) & (tab_entries(WG) - 1u);
+    }
+    return 2;
+}
+
+template <int DIM, int SCOPE, int TABLE_WG = 0>
 __device__ __forceinline__ void expand_site(bool active, uint32_t j, const Geo& g, int8_t* S,
                                             int s0, uint32_t thr, uint32_t k0, uint32_t k1,
                                             uint32_t t, uint32_t s, uint32_t nb[2 * DIM],
-                                            bool won[2 * DIM])
+                                            bool won[2 * DIM], uint32_t* tab = nullptr)
 {
     if (!active) j = 0u;
     uint32_t sa[2 * DIM];
@@ -58,8 +93,24 @@ __device__ __forceinline__ void expand_site(bool active, uint32_t j, const Geo& 
         }
         act[2 * mu + 1] = a;
     }
+    if (TABLE_WG == 0) {
 #pragma unroll
-    for (int m = 0; m < 2 * DIM; ++m) won[m] = act[m] && claim<SCOPE>(S, sa[m], s0);
+        for (int m = 0; m < 2 * DIM; ++m) won[m] = act[m] && claim<SCOPE>(S, sa[m], s0);
+    } else {
+#pragma unroll
+        for (int m = 0; m < 2 * DIM; ++m) {
+            won[m] = false;
+            if (act[m]) {
+                const int r = table_claim<TABLE_WG>(tab, sa[m]);
+                if (r == 1) {
+                    S[sa[m]] = (int8_t)(-s0);
+                    won[m] = true;
+                } else if (r == 2) {
+                    won[m] = claim<SCOPE>(S, sa[m], s0);
+                }
+            }
+        }
+    }
 }
 
 // Wave-level compaction of the claimed sites: one ballot per neighbour slot,
@@ -373,6 +424,7 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
     const bool measure = R->measure != 0u;
     uint32_t err = 0u;
     const uint32_t QC = qmask + 1u;
+    uint32_t* tab = q + QC;                                       // claim table after the ring
 
     uint32_t done = 0u;
     while (done < n) {
@@ -409,11 +461,13 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
 
             uint32_t nb[2 * DIM];
             bool won[2 * DIM];
-            expand_site<DIM, SCOPE_WG>(active, j, g, S, s0, thr, k0, k1, t, s, nb, won);
+            expand_site<DIM, SCOPE_WG, WG>(active, j, g, S, s0, thr, k0, k1, t, s, nb, won, tab);
             uint32_t pos[2 * DIM];
             const uint32_t wtot = wave_compact<DIM>(won, pos);
             if (lane == 0) wave_cnt[wv] = wtot;
             __syncthreads();
+            // the step's claims are settled: empty the table for the next step
+            for (uint32_t i = tid; i < tab_entries(WG); i += WG) tab[i] = TAB_EMPTY;
             uint32_t before = 0u, total = 0u;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
@@ -484,6 +538,7 @@ __global__ __launch_bounds__(WG) void batch_kernel(Rep* reps, const uint32_t* or
         ctl.t_start = wall_clock64();
         ctl.stop = 0u;
     }
+    for (uint32_t i = threadIdx.x; i < tab_entries(WG); i += WG) q[qmask + 1u + i] = TAB_EMPTY;
     __syncthreads();
     uint32_t idx = blockIdx.x;
     while (idx < n_reps) {

@@ -182,6 +182,12 @@ static int device_cus()
 
 using BatchFn = void (*)(Rep*, const uint32_t*, uint32_t, uint32_t*, uint32_t, uint32_t, uint64_t);
 
+// Dynamic LDS of the batched kernel: frontier ring + claim table.
+static size_t batch_lds_bytes(int wg, uint32_t qentries)
+{
+    return ((size_t)qentries + wolff::tab_entries(wg)) * sizeof(uint32_t);
+}
+
 // Batched kernel for a workgroup size and a dimension (2, 3, or 0 for a
 // batch that mixes both; the single-dimension variants need fewer registers).
 static BatchFn batch_fn(int wg, int dims)
@@ -203,7 +209,7 @@ static hipError_t launch_batch(int wg, int dims, uint32_t grid, uint32_t qentrie
                                Rep* reps, const uint32_t* order, uint32_t n, uint32_t* next,
                                uint32_t max_updates, uint64_t budget = 0)
 {
-    const size_t lds = (size_t)qentries * sizeof(uint32_t);
+    const size_t lds = batch_lds_bytes(wg, qentries);
     const uint32_t qmask = qentries - 1u;
     hipLaunchKernelGGL(wolff::reset_counter_kernel, dim3(1), dim3(64), 0, st, next);
     hipLaunchKernelGGL(batch_fn(wg, dims), dim3(grid), dim3(wg), lds, st, reps, order, n, next,
@@ -215,7 +221,7 @@ static hipError_t launch_batch(int wg, int dims, uint32_t grid, uint32_t qentrie
 static int batch_occupancy(int wg, int dims, int qentries)
 {
     int per_cu = 0;
-    const size_t lds = (size_t)qentries * sizeof(uint32_t);
+    const size_t lds = batch_lds_bytes(wg, (uint32_t)qentries);
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &per_cu, reinterpret_cast<const void*>(batch_fn(wg, dims)), wg, lds);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
@@ -225,7 +231,7 @@ static int batch_occupancy(int wg, int dims, int qentries)
 static bool valid_tiles(int wg, int q)
 {
     if (wg != 64 && wg != 128 && wg != 256 && wg != 512 && wg != 1024) return false;
-    if (q < wg || q > 16384 || (q & (q - 1)) != 0) return false;
+    if (q < wg || q > 8192 || (q & (q - 1)) != 0) return false;
     return true;
 }
 
