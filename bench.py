@@ -22,7 +22,6 @@ records are compared with the GPU's for those updates.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -46,12 +45,8 @@ def log(msg):
 
 
 def kernel_source_sha() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1110_0899_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + f.read())
-    return h.hexdigest()[:16]
+    from paper_1110_0899_amd.profiling import kernel_source_sha as sha
+    return sha()
 
 
 def counter_traffic(kernel: str, workload: str):
@@ -240,8 +235,9 @@ def main():
     ap.add_argument("--steps", type=int, default=2000, help="timed updates of the headline leg")
     ap.add_argument("--warmup", type=int, default=1000, help="thermalisation updates")
     ap.add_argument("--legs", default="plain2d,plain3d,batch2d,batch3d,serve")
-    ap.add_argument("--batch-replicas", type=int, default=256)
-    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--batch-replicas", type=int, default=1024)
+    ap.add_argument("--batch-steps", type=int, default=8)
+    ap.add_argument("--batch-warmup", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-leg", default=None,
                     help="run only this leg (plain2d, plain3d, batch2d, batch3d, copy) for a "
@@ -273,12 +269,12 @@ def main():
                                   if k not in ("records", "checkpoint")}
     if "batch2d" in legs:
         extra["batch_2d_L4096"] = batch_leg(binding, workloads, 2, 4096, args.batch_replicas,
-                                            args.warmup // 4, args.batch_steps)
+                                            args.batch_warmup, args.batch_steps)
         extra["batch_2d_L4096"]["vs_plain"] = (extra["batch_2d_L4096"]["added_per_s"]
                                                / main_leg["added_per_s"])
     if "batch3d" in legs:
         extra["batch_3d_L256"] = batch_leg(binding, workloads, 3, 256, args.batch_replicas,
-                                           args.warmup, 5 * args.batch_steps)
+                                           10 * args.batch_warmup, 5 * args.batch_steps)
         if "plain_3d_L256" in extra:
             extra["batch_3d_L256"]["vs_plain"] = (extra["batch_3d_L256"]["added_per_s"]
                                                   / extra["plain_3d_L256"]["added_per_s"])
