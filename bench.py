@@ -117,7 +117,9 @@ def batch_leg(binding, workloads, dim, L, n_rep, warmup, steps, wg=None, q=None)
     tuned = None
     if wg is None or q is None:
         from paper_1110_0899_amd import autotune
-        tjobs = workloads.same_shape_jobs(dim, L, min(n_rep, 128), 16)
+        # tune on the replica count of the run: the best tiles depend on how
+        # full the device is
+        tjobs = workloads.same_shape_jobs(dim, L, n_rep, 16)
         tuned = autotune.tune(tjobs, warm=8, timed=4, start=1, log=log)
         wg, q = tuned["wg"], tuned["queue_entries"]
     b = binding.Batch(jobs, start=1)

@@ -73,6 +73,7 @@ __device__ __forceinline__ void expand_site(bool active, uint32_t j, const Geo& 
 #pragma unroll
     for (int m = 0; m < 2 * DIM; ++m) el[m] = active && (int)S[sa[m]] == s0;
 
+    bool act[2 * DIM];
     uint32_t rp[3] = {0u, 0u, 0u};
     const bool need_plus = el[0] || el[2] || (DIM == 3 && el[2 * (DIM - 1)]);
     if (need_plus) {
@@ -81,7 +82,6 @@ __device__ __forceinline__ void expand_site(bool active, uint32_t j, const Geo& 
         rp[1] = r.y;
         rp[2] = r.z;
     }
-    bool act[2 * DIM];
 #pragma unroll
     for (int mu = 0; mu < DIM; ++mu) {
         act[2 * mu] = el[2 * mu] && rp[mu] < thr;
