@@ -81,8 +81,9 @@ typedef struct wolff_sim wolff_sim;
 
 /* Create a lattice of L^dim spins, iid +-1 from `seed` (update index t = 0).
  * dim in {2, 3}; L >= 2; L^dim < 2^32; J > 0 and T > 0 finite.
- * Allocates about 9 bytes per site of device memory (spins, the overflow
- * queue of the one-workgroup path, the queue of the multi-workgroup path).
+ * Allocates about 6 bytes per site of device memory (spins, the overflow
+ * stack and member list of the one-workgroup path), plus 8 bytes per site
+ * for the multi-workgroup queue on the first team-path run.
  * Synchronises before returning.  *out is set only on success. */
 int wolff_create(int dim, int L, double J, double T, uint64_t seed, wolff_sim **out);
 
@@ -112,8 +113,10 @@ int wolff_get_spins(wolff_sim *s, int8_t *host, uint64_t n);
  * are dropped and the observables recomputed. */
 int wolff_set_spins(wolff_sim *s, const int8_t *host, uint64_t n, uint64_t t);
 
-/* 1: compute bond_sum after every update by a pass over the lattice (the
- * paper's "+ measurement"); 0: "update only", bond_sum = WOLFF_NOT_MEASURED.
+/* 1: bond_sum after every update (the paper's "+ measurement"): the
+ * one-workgroup path updates it exactly from the cluster's boundary (a pass
+ * over the members' neighbours), the team path and large clusters recount it
+ * over the lattice; 0: "update only", bond_sum = WOLFF_NOT_MEASURED.
  * mag and csize are exact in both modes.  Default 1. */
 int wolff_set_measure(wolff_sim *s, int on);
 
@@ -216,8 +219,8 @@ int wolff_batch_last_ms(wolff_batch *b, double *ms);
  * resident job in time-bounded quanta, each one persistent launch of the
  * batched kernel (continuous batching).  Jobs are admitted first-in
  * first-out while a workgroup slot and their HBM footprint are free
- * (footprint = spins + overflow stack + records: about 5 N + 24 n_updates
- * bytes); a job submitted while others run joins the next quantum, so its
+ * (footprint = spins + overflow stack + member list + records: about
+ * 6 N + 24 n_updates bytes); a job submitted while others run joins the next quantum, so its
  * updates overlap with theirs on the device.  Every job's records are
  * exactly those of the same job run alone (the random stream is keyed by the
  * job's own seed and update index, never by its neighbours in the batch).

@@ -179,16 +179,39 @@ __device__ __forceinline__ void neighbours(const Geo& g, uint32_t j, uint32_t nb
 // to s0: that caller owns k.  A flipped member reads -s0 and is never
 // eligible again, which makes the spin itself the visit mark of the update:
 // no separate mark array, nothing to clear between updates.
-template <int SCOPE>
+//
+// Tagged claims (TAG = true) additionally mark the byte as a member of the
+// current cluster: +1 -> 0xBF (OR 0xBE), -1 -> 0x41 (AND 0x41).  Bit 1 still
+// holds the sign (set exactly for -1), so every sign test and the popcount
+// reductions read tagged bytes correctly, and a tagged byte never equals
+// +-1, so it is never eligible.  Bits 6 and 7 differ exactly on tagged
+// bytes.  The update that tags members clears the tags before it ends.
+constexpr uint8_t TAGGED_MINUS = 0xBF;   // -1, member of the current cluster
+constexpr uint8_t TAGGED_PLUS = 0x41;    // +1, member of the current cluster
+
+__device__ __forceinline__ bool is_tagged(int8_t b)
+{
+    const uint32_t u = (uint8_t)b;
+    return ((u >> 6) ^ (u >> 7)) & 1u;
+}
+
+__device__ __forceinline__ int8_t tagged_flip(int s0)
+{
+    return (int8_t)(s0 > 0 ? TAGGED_MINUS : TAGGED_PLUS);
+}
+
+template <int SCOPE, bool TAG = false>
 __device__ __forceinline__ bool claim(int8_t* S, uint32_t k, int s0)
 {
     uint32_t* w = reinterpret_cast<uint32_t*>(S) + (k >> 2);
     const uint32_t sh = (k & 3u) * 8u;
     if (s0 > 0) {
-        const uint32_t old = __hip_atomic_fetch_or(w, 0xFEu << sh, __ATOMIC_RELAXED, SCOPE);
+        const uint32_t m = (TAG ? 0xBEu : 0xFEu) << sh;
+        const uint32_t old = __hip_atomic_fetch_or(w, m, __ATOMIC_RELAXED, SCOPE);
         return ((old >> sh) & 0xFFu) == 0x01u;
     } else {
-        const uint32_t old = __hip_atomic_fetch_and(w, ~(0xFEu << sh), __ATOMIC_RELAXED, SCOPE);
+        const uint32_t m = ~((TAG ? 0xBEu : 0xFEu) << sh);
+        const uint32_t old = __hip_atomic_fetch_and(w, m, __ATOMIC_RELAXED, SCOPE);
         return ((old >> sh) & 0xFFu) == 0xFFu;
     }
 }

@@ -103,10 +103,10 @@ __device__ __forceinline__ void expand_site(bool active, uint32_t j, const Geo& 
             if (act[m]) {
                 const int r = table_claim<TABLE_WG>(tab, sa[m]);
                 if (r == 1) {
-                    S[sa[m]] = (int8_t)(-s0);
+                    S[sa[m]] = tagged_flip(s0);
                     won[m] = true;
                 } else if (r == 2) {
-                    won[m] = claim<SCOPE>(S, sa[m], s0);
+                    won[m] = claim<SCOPE, true>(S, sa[m], s0);
                 }
             }
         }
@@ -381,6 +381,26 @@ __device__ __forceinline__ void reduce_lattice_wg(const int8_t* S, const Geo& g,
     __syncthreads();
 }
 
+// Remove the member tags from a whole lattice (used when the member list
+// overflowed): every byte becomes its plain +-1 from bit 1.
+template <int WG>
+__device__ __forceinline__ void clear_tags_wg(int8_t* S, uint32_t N)
+{
+    uint32_t* W = reinterpret_cast<uint32_t*>(S);
+    const uint32_t nw = (N + 3u) >> 2;
+    for (uint32_t i = threadIdx.x; i < nw; i += WG) {
+        const uint32_t w = W[i];
+        const uint32_t neg = (w >> 1) & 0x01010101u;              // 1 where the spin is -1
+        uint32_t clean = 0x01010101u | (neg * 0xFEu);
+        if (4u * i + 4u > N) {                                    // keep the padding bytes
+            const uint32_t keep = 0xFFFFFFFFu << (8u * (N - 4u * i));
+            clean = (clean & ~keep) | (w & keep);
+        }
+        if (clean != w) W[i] = clean;
+    }
+    __syncthreads();
+}
+
 // ------------------------------------------------- one-workgroup growth path
 // All updates of one lattice in one workgroup.  The frontier is a ring of
 // `qmask + 1` entries in LDS; when a step's new sites do not fit, they go to
@@ -414,6 +434,8 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
 
     int8_t* S = R->S;
     uint32_t* ov = R->ov;
+    uint32_t* members = R->members;
+    const uint32_t mcap = R->mcap;
     const Geo g = R->geo;
     const uint32_t thr = R->thr, k0 = R->k0, k1 = R->k1;
     const uint32_t t0 = R->t;
@@ -421,6 +443,7 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
     if (max_updates != 0u && max_updates < n) n = max_updates;
     wolff_record* rec = R->rec + R->rec_count;
     int64_t M = R->M, B = R->B;
+    bool b_valid = R->b_valid != 0u;
     const bool measure = R->measure != 0u;
     uint32_t err = 0u;
     const uint32_t QC = qmask + 1u;
@@ -434,7 +457,7 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
         if (tid == 0) {
             const uint32_t a = site_addr<DIM>(g, s);
             const int s0 = S[a];
-            claim<SCOPE_WG>(S, a, s0);
+            S[a] = tagged_flip(s0);
             q[0] = s;
             ctl->s0 = s0;
         }
@@ -443,6 +466,7 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
 
         uint32_t head = 0u, tail = 1u, ovn = 0u;                    // the paper's in / ic
         uint64_t csize = 1u;
+        uint32_t listed = 0u;                                       // members written to the list
         while (true) {
             uint32_t avail = tail - head;
             if (avail < (uint32_t)WG && ovn > 0u) {                 // refill the ring
@@ -458,6 +482,9 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
             const bool active = tid < nproc;
             const uint32_t j = active ? q[(head + tid) & qmask] : 0u;
             head += nproc;
+            // every member is expanded exactly once: list it for the post-pass
+            if (active && listed + tid < mcap) members[listed + tid] = j;
+            listed += nproc;
 
             uint32_t nb[2 * DIM];
             bool won[2 * DIM];
@@ -491,10 +518,43 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
         }
 
         M -= 2 * (int64_t)s0 * (int64_t)csize;                     // exact |dM| = 2|C|
-        if (measure) {
+        const bool complete = listed <= mcap;                       // the list holds the cluster
+        if (complete && measure && b_valid) {
+            // dB = -2 s0 sum_{i in C} sum_{k ~ i, k not in C} S_k: members are
+            // tagged, every untagged neighbour byte is its +-1 spin
+            int32_t qsum = 0;
+            for (uint32_t e = tid; e < listed; e += WG) {
+                uint32_t nb[2 * DIM], sa[2 * DIM];
+                neighbours<DIM>(g, members[e], nb, sa);
+#pragma unroll
+                for (int m = 0; m < 2 * DIM; ++m) {
+                    const int8_t b = S[sa[m]];
+                    qsum += is_tagged(b) ? 0 : (int32_t)b;
+                }
+            }
+            const int64_t wq = wave_sum_i64((int64_t)qsum);
+            if (lane == 0) red[wv] = wq;
+            __syncthreads();
+            int64_t Q = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) Q += red[w];
+            B -= 2 * (int64_t)s0 * Q;
+        }
+        if (!measure || !complete) b_valid = false;
+        if (complete) {
+            __syncthreads();                                        // all tags read before clearing
+            for (uint32_t e = tid; e < listed; e += WG) S[site_addr<DIM>(g, members[e])] = (int8_t)(-s0);
+            __syncthreads();
+        } else {
+            clear_tags_wg<WG>(S, g.N);
+        }
+        if (measure && !b_valid) {
+            // a full pass: first measured update after "update only", or a
+            // cluster larger than the member list
             int64_t Bm, Mm;
             reduce_lattice_wg<WG, DIM>(S, g, red, Bm, Mm);
             B = Bm;
+            b_valid = true;
             if (Mm != M) err |= ERR_MAG;
         }
         if (tid == 0) {
@@ -515,6 +575,7 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
         R->rec_count += done;
         R->M = M;
         R->B = B;
+        R->b_valid = b_valid ? 1u : 0u;
         R->err |= err;
     }
 }
@@ -591,6 +652,7 @@ __global__ __launch_bounds__(WG) void measure_rep_kernel(Rep* R)
     if (threadIdx.x == 0) {
         R->B = B;
         R->M = M;
+        R->b_valid = 1u;
     }
 }
 
@@ -779,6 +841,7 @@ __global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned
             const int64_t M = R->M - 2 * (int64_t)s0 * (int64_t)csize;
             R->M = M;
             if (R->measure == 0u) {
+                R->b_valid = 0u;
                 wolff_record r;
                 r.bond_sum = (int64_t)WOLFF_NOT_MEASURED;
                 r.mag = M;
@@ -825,6 +888,7 @@ __global__ __launch_bounds__(256) void measure_grid_kernel(Rep* R, TeamCtl* ctl)
             const int64_t M = R->M;
             if (Mm != M) R->err |= ERR_MAG;
             R->B = B;
+            R->b_valid = 1u;
             wolff_record r;
             r.bond_sum = B;
             r.mag = M;

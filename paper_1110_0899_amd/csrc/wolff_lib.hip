@@ -165,6 +165,13 @@ static constexpr uint64_t T_LIMIT = 0xFFFFFFFEull;   // t + 1 must fit the 32-bi
 
 static uint64_t padded_bytes(uint64_t N) { return (N + 255u) & ~uint64_t(255); }
 
+// Member-list entries of the one-workgroup path: the whole lattice for small
+// lattices, a quarter of it otherwise (a larger cluster is measured by a full
+// lattice pass, which is then the cheaper way anyway).  The list lives after
+// the N-entry overflow stack in the same allocation.
+static uint64_t member_cap(uint64_t N) { return std::max<uint64_t>(N / 4, std::min<uint64_t>(N, 65536)); }
+static uint64_t queue_entries(uint64_t N) { return N + member_cap(N); }
+
 // -------------------------------------------------------- kernel dispatch
 static int g_num_cus = 0;
 
@@ -403,7 +410,7 @@ extern "C" int wolff_create(int dim, int L, double J, double T, uint64_t seed, w
     s->stream = s->own_stream;
     CREATE_TRY(hipMalloc(&s->S, padded_bytes(N)));
     CREATE_TRY(hipMemset(s->S, 0, padded_bytes(N)));
-    CREATE_TRY(hipMalloc(&s->ov, N * sizeof(uint32_t)));
+    CREATE_TRY(hipMalloc(&s->ov, queue_entries(N) * sizeof(uint32_t)));
     CREATE_TRY(hipMalloc(&s->d_rep, sizeof(Rep)));
     CREATE_TRY(hipMalloc(&s->d_order, sizeof(uint32_t)));
     CREATE_TRY(hipMalloc(&s->d_next, sizeof(uint32_t)));
@@ -421,6 +428,8 @@ extern "C" int wolff_create(int dim, int L, double J, double T, uint64_t seed, w
     Rep r{};
     r.S = s->S;
     r.ov = s->ov;
+    r.members = s->ov + N;
+    r.mcap = (uint32_t)member_cap(N);
     r.rec = s->d_rec;
     r.rec_count = 0;
     r.geo = s->geo;
@@ -846,7 +855,7 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
         b->ov_off.push_back(ov_total);
         b->rec_off.push_back(rec_total);
         s_total += padded_bytes(N);
-        ov_total += N;
+        ov_total += queue_entries(N);
         rec_total += std::max<uint64_t>(jobs[i].n_updates, 1);
     }
     b->jobs.assign(jobs, jobs + n_jobs);
@@ -871,6 +880,8 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
         r = Rep{};
         r.S = b->S + b->S_off[i];
         r.ov = b->ov + b->ov_off[i];
+        r.members = r.ov + Ns[i];
+        r.mcap = (uint32_t)member_cap(Ns[i]);
         r.rec = b->rec + b->rec_off[i];
         r.rec_count = 0;
         r.geo = make_geo(j.dim, (uint32_t)j.L);
@@ -1071,7 +1082,7 @@ struct SrvJob {
 
 uint64_t job_footprint(uint64_t N, uint64_t n_updates)
 {
-    return padded_bytes(N) + ((4 * N + 255) & ~uint64_t(255)) +
+    return padded_bytes(N) + ((4 * queue_entries(N) + 255) & ~uint64_t(255)) +
            std::max<uint64_t>(n_updates, 1) * sizeof(wolff_record) + 256;
 }
 
@@ -1199,7 +1210,7 @@ static int server_admit(wolff_server* v)
         j.block = blk;
         int8_t* S = (int8_t*)blk;
         uint32_t* ov = (uint32_t*)((char*)blk + padded_bytes(j.N));
-        wolff_record* rec = (wolff_record*)((char*)ov + ((4 * j.N + 255) & ~uint64_t(255)));
+        wolff_record* rec = (wolff_record*)((char*)ov + ((4 * queue_entries(j.N) + 255) & ~uint64_t(255)));
         HIP_TRY(hipMemsetAsync(S, 0, padded_bytes(j.N), v->stream));
         if (j.spec.start == 0) {
             hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((j.N + 255) / 256, 65536)),
@@ -1213,6 +1224,8 @@ static int server_admit(wolff_server* v)
         r = Rep{};
         r.S = S;
         r.ov = ov;
+        r.members = ov + j.N;
+        r.mcap = (uint32_t)member_cap(j.N);
         r.rec = rec;
         r.rec_count = 0;
         r.geo = make_geo(j.spec.dim, (uint32_t)j.spec.L);

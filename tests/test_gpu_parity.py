@@ -92,7 +92,9 @@ def check_cold(path):
     # T well below T_c from the ordered state: clusters cover most of the
     # lattice, the frontier outgrows the LDS ring and the overflow stack /
     # global queue is used.
-    for dim, L, T, n in [(2, 256, 1.5, 30), (3, 40, 3.0, 20)]:
+    # (L=512 / 3D L=64 have more sites than their member lists hold: clusters
+    # above N/4 take the full-lattice measurement and tag clearing)
+    for dim, L, T, n in [(2, 256, 1.5, 30), (3, 40, 3.0, 20), (2, 512, 1.8, 12), (3, 64, 3.5, 8)]:
         N = L ** dim
         start = np.ones(N, dtype=np.int8)
         print("case cold dim=%d L=%d T=%.3f path=%d" % (dim, L, T, path), flush=True)
@@ -238,3 +240,23 @@ def test_batch_graph_replays_match_oracle():
             ref, Sref = oracle_series(j.dim, j.L, j.T, j.seed, j.n_updates)
             assert (as_array(b.records(i)) == ref).all()
             assert (b.spins(i) == Sref).all()
+
+
+def test_measure_switch_midway():
+    # measured, update-only, measured again: the energy after the switch back
+    # must come from a fresh lattice pass, not from a stale running sum
+    dim, L, T, seed = 2, 64, TC2, 71
+    ref, Sref = oracle_series(dim, L, T, seed, 300)
+    for path in (binding.PATH_SINGLE, binding.PATH_TEAM):
+        with binding.Simulation(dim, L, 1.0, T, seed) as sim:
+            sim.set_path(path, 8)
+            sim.run(100)
+            sim.set_measure(False)
+            sim.run(100)
+            sim.set_measure(True)
+            sim.run(100)
+            got = as_array(sim.observables())
+        assert (got[:100] == ref[:100]).all()
+        assert (got[100:200, 0] == binding.NOT_MEASURED).all()
+        assert (got[100:200, 1:] == ref[100:200, 1:]).all()
+        assert (got[200:] == ref[200:]).all(), path
