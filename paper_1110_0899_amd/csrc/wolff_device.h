@@ -114,11 +114,28 @@ __device__ __forceinline__ uint32_t site_addr(const Geo& g, uint32_t j)
     return g.tile_addr<3>(x, q - r * g.L, r);
 }
 
+// Storage address of site j and its sublattice parity (x + y (+ z)) mod 2.
+template <int DIM>
+__device__ __forceinline__ uint32_t site_addr_parity(const Geo& g, uint32_t j, uint32_t& par)
+{
+    const uint32_t q = g.div_L(j);
+    const uint32_t x = j - q * g.L;
+    if (DIM == 2) {
+        par = (x + q) & 1u;
+        return g.tiled ? g.tile_addr<2>(x, q, 0u) : j;
+    }
+    const uint32_t r = g.div_L(q);
+    const uint32_t y = q - r * g.L;
+    par = (x + y + r) & 1u;
+    return g.tiled ? g.tile_addr<3>(x, y, r) : j;
+}
+
 // Neighbours of j in slot order (+x, -x, +y, -y[, +z, -z]): logical indices
-// nb[] and storage addresses sa[].
+// nb[] and storage addresses sa[]; also the storage address of j itself and
+// its sublattice parity (x + y (+ z)) mod 2.
 template <int DIM>
 __device__ __forceinline__ void neighbours(const Geo& g, uint32_t j, uint32_t nb[2 * DIM],
-                                           uint32_t sa[2 * DIM])
+                                           uint32_t sa[2 * DIM], uint32_t& self, uint32_t& par)
 {
     const uint32_t L = g.L;
     const uint32_t q = g.div_L(j);
@@ -132,14 +149,17 @@ __device__ __forceinline__ void neighbours(const Geo& g, uint32_t j, uint32_t nb
         const uint32_t y = q;
         nb[2] = (j >= N - L) ? j - (N - L) : j + L;
         nb[3] = (j >= L) ? j - L : j + (N - L);
+        par = (x + y) & 1u;
         if (g.tiled) {
             const uint32_t yp = (y + 1u == L) ? 0u : y + 1u;
             const uint32_t ym = (y == 0u) ? L - 1u : y - 1u;
+            self = g.tile_addr<2>(x, y, 0u);
             sa[0] = g.tile_addr<2>(xp, y, 0u);
             sa[1] = g.tile_addr<2>(xm, y, 0u);
             sa[2] = g.tile_addr<2>(x, yp, 0u);
             sa[3] = g.tile_addr<2>(x, ym, 0u);
         } else {
+            self = j;
 #pragma unroll
             for (int m = 0; m < 4; ++m) sa[m] = nb[m];
         }
@@ -152,11 +172,13 @@ __device__ __forceinline__ void neighbours(const Geo& g, uint32_t j, uint32_t nb
         nb[3] = (y == 0u) ? j + LL - L : j - L;
         nb[4] = (j >= N - LL) ? j - (N - LL) : j + LL;
         nb[5] = (j >= LL) ? j - LL : j + (N - LL);
+        par = (x + y + z) & 1u;
         if (g.tiled) {
             const uint32_t yp = (y + 1u == L) ? 0u : y + 1u;
             const uint32_t ym = (y == 0u) ? L - 1u : y - 1u;
             const uint32_t zp = (z + 1u == L) ? 0u : z + 1u;
             const uint32_t zm = (z == 0u) ? L - 1u : z - 1u;
+            self = g.tile_addr<3>(x, y, z);
             sa[0] = g.tile_addr<3>(xp, y, z);
             sa[1] = g.tile_addr<3>(xm, y, z);
             sa[2] = g.tile_addr<3>(x, yp, z);
@@ -164,10 +186,19 @@ __device__ __forceinline__ void neighbours(const Geo& g, uint32_t j, uint32_t nb
             sa[4] = g.tile_addr<3>(x, y, zp);
             sa[5] = g.tile_addr<3>(x, y, zm);
         } else {
+            self = j;
 #pragma unroll
             for (int m = 0; m < 6; ++m) sa[m] = nb[m];
         }
     }
+}
+
+template <int DIM>
+__device__ __forceinline__ void neighbours(const Geo& g, uint32_t j, uint32_t nb[2 * DIM],
+                                           uint32_t sa[2 * DIM])
+{
+    uint32_t self, par;
+    neighbours<DIM>(g, j, nb, sa, self, par);
 }
 
 // ------------------------------------------------------------ claim + flip
@@ -179,41 +210,53 @@ __device__ __forceinline__ void neighbours(const Geo& g, uint32_t j, uint32_t nb
 // to s0: that caller owns k.  A flipped member reads -s0 and is never
 // eligible again, which makes the spin itself the visit mark of the update:
 // no separate mark array, nothing to clear between updates.
-//
-// Tagged claims (TAG = true) additionally mark the byte as a member of the
-// current cluster: +1 -> 0xBF (OR 0xBE), -1 -> 0x41 (AND 0x41).  Bit 1 still
-// holds the sign (set exactly for -1), so every sign test and the popcount
-// reductions read tagged bytes correctly, and a tagged byte never equals
-// +-1, so it is never eligible.  Bits 6 and 7 differ exactly on tagged
-// bytes.  The update that tags members clears the tags before it ends.
-constexpr uint8_t TAGGED_MINUS = 0xBF;   // -1, member of the current cluster
-constexpr uint8_t TAGGED_PLUS = 0x41;    // +1, member of the current cluster
-
-__device__ __forceinline__ bool is_tagged(int8_t b)
-{
-    const uint32_t u = (uint8_t)b;
-    return ((u >> 6) ^ (u >> 7)) & 1u;
-}
-
-__device__ __forceinline__ int8_t tagged_flip(int s0)
-{
-    return (int8_t)(s0 > 0 ? TAGGED_MINUS : TAGGED_PLUS);
-}
-
-template <int SCOPE, bool TAG = false>
+template <int SCOPE>
 __device__ __forceinline__ bool claim(int8_t* S, uint32_t k, int s0)
 {
     uint32_t* w = reinterpret_cast<uint32_t*>(S) + (k >> 2);
     const uint32_t sh = (k & 3u) * 8u;
     if (s0 > 0) {
-        const uint32_t m = (TAG ? 0xBEu : 0xFEu) << sh;
+        const uint32_t m = 0xFEu << sh;
         const uint32_t old = __hip_atomic_fetch_or(w, m, __ATOMIC_RELAXED, SCOPE);
         return ((old >> sh) & 0xFFu) == 0x01u;
     } else {
-        const uint32_t m = ~((TAG ? 0xBEu : 0xFEu) << sh);
+        const uint32_t m = ~(0xFEu << sh);
         const uint32_t old = __hip_atomic_fetch_and(w, m, __ATOMIC_RELAXED, SCOPE);
         return ((old >> sh) & 0xFFu) == 0xFFu;
     }
+}
+
+// ------------------------------------------------------------ member tags
+// The one-workgroup path can instead tag the members of the current cluster,
+// which is what lets it update the bond sum from the cluster alone.  A plain
+// spin has bit 0 set (+1 = 0x01, -1 = 0xFF); a tagged byte has bit 0 clear:
+//   bits 7..3  epoch: the update index mod 32
+//   bit 2      1 once the member has been expanded
+//   bit 1      the sign, as in a plain spin (set exactly for -1)
+// Bit 1 is the sign of every byte, so the popcount reductions and the host
+// copies read tagged bytes unchanged.  A tag of another epoch is read as the
+// plain spin it carries, so tags need no clearing after an update; the
+// lattice is normalised before an epoch could come round again.
+constexpr uint32_t TAG_EPOCHS = 32u;
+constexpr uint32_t NO_TAG = 0x100u;      // tag key that no byte matches
+
+__device__ __forceinline__ uint32_t tag_key(uint32_t t) { return (t & (TAG_EPOCHS - 1u)) << 3; }
+
+// member of the current cluster (either state) / expanded member
+__device__ __forceinline__ bool is_member(uint32_t b, uint32_t key) { return (b & 0xF9u) == key; }
+__device__ __forceinline__ bool is_expanded(uint32_t b, uint32_t key) { return (b & 0xFDu) == (key | 4u); }
+
+// Byte of a site claimed for a cluster of spin s0 (its new spin is -s0):
+// tagged with `key`, or the plain spin when key == NO_TAG.
+__device__ __forceinline__ int8_t claimed_byte(int s0, uint32_t key)
+{
+    if (key == NO_TAG) return (int8_t)(s0 > 0 ? -1 : 1);
+    return (int8_t)(key | (s0 > 0 ? 2u : 0u));
+}
+
+__device__ __forceinline__ int8_t expanded_byte(int s0, uint32_t key)
+{
+    return (int8_t)(key | 4u | (s0 > 0 ? 2u : 0u));
 }
 
 // ------------------------------------------------------------ wave helpers

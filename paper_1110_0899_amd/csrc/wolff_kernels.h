@@ -23,7 +23,6 @@ namespace wolff {
 struct Rep {
     int8_t* S;              // spins, N bytes (allocation padded to a multiple of 4)
     uint32_t* ov;           // overflow stack of the one-workgroup path, N entries
-    uint32_t* members;      // member list of the one-workgroup path, mcap entries
     wolff_record* rec;      // record array
     uint64_t rec_count;     // records written so far
     Geo geo;
@@ -34,7 +33,7 @@ struct Rep {
     uint32_t n_left;        // updates still to run
     uint32_t measure;       // 1: bond sum in every record
     uint32_t err;           // error bits (ERR_*)
-    uint32_t mcap;          // member list capacity
+    uint32_t t_norm;        // no member tag in S is older than update t_norm
     uint32_t b_valid;       // 1: B holds the bond sum of the current lattice
     int64_t M;              // magnetisation after the last update
     int64_t B;              // bond sum (valid when b_valid)

@@ -10,6 +10,7 @@ constexpr int WAVE = 64;
 // Error bits of Rep::err.
 constexpr uint32_t ERR_MAG = 1u;          // magnetisation recount != tracked value
 constexpr uint32_t ERR_TEAM_WAIT = 2u;    // a team wait passed its bound
+constexpr uint32_t ERR_BOND = 4u;         // bond-sum recount != tracked value
 // Bound on the polls of one team wait (each poll is at least ~100 ns, so the
 // bound is seconds, far above any legitimate wait).
 constexpr uint32_t TEAM_SPIN_LIMIT = 1u << 26;
@@ -25,55 +26,11 @@ constexpr int SCOPE_AGENT = __HIP_MEMORY_SCOPE_AGENT;
 // One Philox block serves all +mu bonds of j.  Random words are only drawn
 // for eligible neighbours; the cluster does not depend on which thread
 // claims a site first, so no ordering between threads is needed.
-// Claim table of the one-workgroup path.  Only one workgroup touches the
-// lattice during a launch, so the only races on a site are between threads
-// of the same step: they are settled in an LDS hash table keyed by storage
-// address (CAS on an empty slot), and the winner flips the spin with a plain
-// byte store, visible to the next step after the step's barrier.  A probe
-// sequence longer than TAB_PROBES falls back to the atomic claim on the spin
-// word; the fallback is consistent because slots only fill during a step, so
-// every thread probing a given site either finds its entry or finds the same
-// full window.  The workgroup empties the whole table after each step.
-constexpr uint32_t TAB_EMPTY = 0xFFFFFFFFu;
-constexpr uint32_t TAB_PROBES = 32u;
-
-// Table entries for a workgroup size: 8 per thread (a step claims at most
-// 2d per thread, and usually far fewer).
-__host__ __device__ constexpr uint32_t tab_entries(int wg) { return 8u * (uint32_t)wg; }
-__host__ __device__ constexpr uint32_t tab_shift(int wg)
+template <int DIM>
+__device__ __forceinline__ void active_bonds(const bool el[2 * DIM], uint32_t j,
+                                             const uint32_t nb[2 * DIM], uint32_t thr, uint32_t k0,
+                                             uint32_t k1, uint32_t t, uint32_t s, bool act[2 * DIM])
 {
-    return wg == 64 ? 23u : wg == 128 ? 22u : wg == 256 ? 21u : wg == 512 ? 20u : 19u;
-}
-
-// 1: won through the table; 0: another thread holds the site;
-// 2: no free slot within the probe window (use the atomic claim).
-template <int WG>
-__device__ __forceinline__ int table_claim(uint32_t* tab, uint32_t a)
-{
-    uint32_t h = (a * 0x9E3779B1u) >> tab_shift(WG);
-    for (uint32_t p = 0; p < TAB_PROBES; ++p) {
-        const uint32_t prev = atomicCAS(&tab[h], TAB_EMPTY, a);
-        if (prev == TAB_EMPTY) return 1;
-        if (prev == a) return 0;
-        h = (h + 1u) & (tab_entries(WG) - 1u);
-    }
-    return 2;
-}
-
-template <int DIM, int SCOPE, int TABLE_WG = 0>
-__device__ __forceinline__ void expand_site(bool active, uint32_t j, const Geo& g, int8_t* S,
-                                            int s0, uint32_t thr, uint32_t k0, uint32_t k1,
-                                            uint32_t t, uint32_t s, uint32_t nb[2 * DIM],
-                                            bool won[2 * DIM], uint32_t* tab = nullptr)
-{
-    if (!active) j = 0u;
-    uint32_t sa[2 * DIM];
-    neighbours<DIM>(g, j, nb, sa);
-    bool el[2 * DIM];
-#pragma unroll
-    for (int m = 0; m < 2 * DIM; ++m) el[m] = active && (int)S[sa[m]] == s0;
-
-    bool act[2 * DIM];
     uint32_t rp[3] = {0u, 0u, 0u};
     const bool need_plus = el[0] || el[2] || (DIM == 3 && el[2 * (DIM - 1)]);
     if (need_plus) {
@@ -93,23 +50,88 @@ __device__ __forceinline__ void expand_site(bool active, uint32_t j, const Geo& 
         }
         act[2 * mu + 1] = a;
     }
-    if (TABLE_WG == 0) {
+}
+
+// Team path: spins are plain bytes and a claim is the atomic flip.
+template <int DIM, int SCOPE>
+__device__ __forceinline__ void expand_site(bool active, uint32_t j, const Geo& g, int8_t* S,
+                                            int s0, uint32_t thr, uint32_t k0, uint32_t k1,
+                                            uint32_t t, uint32_t s, uint32_t nb[2 * DIM],
+                                            bool won[2 * DIM])
+{
+    if (!active) j = 0u;
+    uint32_t sa[2 * DIM];
+    neighbours<DIM>(g, j, nb, sa);
+    bool el[2 * DIM];
 #pragma unroll
-        for (int m = 0; m < 2 * DIM; ++m) won[m] = act[m] && claim<SCOPE>(S, sa[m], s0);
-    } else {
+    for (int m = 0; m < 2 * DIM; ++m) el[m] = active && (int)S[sa[m]] == s0;
+    bool act[2 * DIM];
+    active_bonds<DIM>(el, j, nb, thr, k0, k1, t, s, act);
 #pragma unroll
-        for (int m = 0; m < 2 * DIM; ++m) {
-            won[m] = false;
-            if (act[m]) {
-                const int r = table_claim<TABLE_WG>(tab, sa[m]);
-                if (r == 1) {
-                    S[sa[m]] = tagged_flip(s0);
-                    won[m] = true;
-                } else if (r == 2) {
-                    won[m] = claim<SCOPE, true>(S, sa[m], s0);
-                }
-            }
-        }
+    for (int m = 0; m < 2 * DIM; ++m) won[m] = act[m] && claim<SCOPE>(S, sa[m], s0);
+}
+
+// Claim table of the one-workgroup path.  Only one workgroup touches the
+// lattice during a launch, so the only races on a site are between threads
+// of the same step: they are settled in an LDS hash table keyed by storage
+// address (CAS on an empty slot, linear probing), and the winner writes the
+// claimed byte with a plain store, visible to the next step after the
+// step's barrier.  A step inserts at most 2d keys per thread, fewer than the
+// table's 8 slots per thread, so a probe always ends at the key or at an
+// empty slot.  The workgroup empties the table after each step.
+constexpr uint32_t TAB_EMPTY = 0xFFFFFFFFu;
+
+// Table entries for a workgroup size: 8 per thread.
+__host__ __device__ constexpr uint32_t tab_entries(int wg) { return 8u * (uint32_t)wg; }
+__host__ __device__ constexpr uint32_t tab_shift(int wg)
+{
+    return wg == 64 ? 23u : wg == 128 ? 22u : wg == 256 ? 21u : wg == 512 ? 20u : 19u;
+}
+
+// true: this thread won site a for the step.
+template <int WG>
+__device__ __forceinline__ bool table_claim(uint32_t* tab, uint32_t a)
+{
+    uint32_t h = (a * 0x9E3779B1u) >> tab_shift(WG);
+    for (uint32_t p = 0; p < tab_entries(WG); ++p) {
+        const uint32_t prev = atomicCAS(&tab[h], TAB_EMPTY, a);
+        if (prev == TAB_EMPTY) return true;
+        if (prev == a) return false;
+        h = (h + 1u) & (tab_entries(WG) - 1u);
+    }
+    return false;   // unreachable: the table always has an empty slot
+}
+
+// One-workgroup path.  `key` is the tag of the update (NO_TAG: plain bytes).
+// Members of the cluster hold -s0, so a neighbour is eligible exactly when
+// its sign is s0.  A neighbour of sign -s0 is a member (original spin s0)
+// or an anti-aligned non-member, counted in n_anti; members already
+// expanded are counted in n_inner (see run_rep).
+template <int DIM, int WG>
+__device__ __forceinline__ void expand_site_wg(bool active, uint32_t j, const uint32_t nb[2 * DIM],
+                                               const uint32_t sa[2 * DIM], int8_t* S, int s0,
+                                               uint32_t key, uint32_t thr, uint32_t k0,
+                                               uint32_t k1, uint32_t t, uint32_t s,
+                                               bool won[2 * DIM], uint32_t* tab,
+                                               uint32_t& n_anti, uint32_t& n_inner)
+{
+    const uint32_t neg0 = s0 < 0 ? 2u : 0u;            // bit 1 of an s0 byte
+    bool el[2 * DIM];
+#pragma unroll
+    for (int m = 0; m < 2 * DIM; ++m) {
+        const uint32_t b = (uint8_t)S[sa[m]];
+        const bool same = (b & 2u) == neg0;
+        el[m] = active && same;
+        n_anti += (active && !same && !is_member(b, key)) ? 1u : 0u;
+        n_inner += (active && is_expanded(b, key)) ? 1u : 0u;
+    }
+    bool act[2 * DIM];
+    active_bonds<DIM>(el, j, nb, thr, k0, k1, t, s, act);
+    const int8_t cb = claimed_byte(s0, key);
+#pragma unroll
+    for (int m = 0; m < 2 * DIM; ++m) {
+        won[m] = act[m] && table_claim<WG>(tab, sa[m]);
+        if (won[m]) S[sa[m]] = cb;
     }
 }
 
@@ -258,19 +280,20 @@ __device__ __forceinline__ void scalar_counts(const int8_t* S, const Geo& g, uin
     const uint32_t dx = stride - dq * L;
     const uint32_t dq_mod = dq - g.div_L(dq) * L;
     uint32_t d = 0u, neg = 0u;
+    // only bit 1 (the sign) of a byte is read: bytes may carry member tags
     for (uint32_t i = first; i < N; i += stride) {
-        const int8_t si = S[i];
+        const uint32_t si = (uint8_t)S[i];
         const uint32_t xp = (x + 1u == L) ? i + 1u - L : i + 1u;
-        d += (S[xp] != si);
+        d += (((uint8_t)S[xp] ^ si) >> 1) & 1u;
         if (DIM == 2) {
             const uint32_t yp = (i >= N - L) ? i - (N - L) : i + L;
-            d += (S[yp] != si);
+            d += (((uint8_t)S[yp] ^ si) >> 1) & 1u;
         } else {
             const uint32_t yp = (y + 1u == L) ? i + L - LL : i + L;
             const uint32_t zp = (i >= N - LL) ? i - (N - LL) : i + LL;
-            d += (S[yp] != si) + (S[zp] != si);
+            d += ((((uint8_t)S[yp] ^ si) >> 1) & 1u) + ((((uint8_t)S[zp] ^ si) >> 1) & 1u);
         }
-        neg += (si < 0);
+        neg += (si >> 1) & 1u;
         x += dx;
         uint32_t carry = 0u;
         if (x >= L) {
@@ -381,8 +404,20 @@ __device__ __forceinline__ void reduce_lattice_wg(const int8_t* S, const Geo& g,
     __syncthreads();
 }
 
-// Remove the member tags from a whole lattice (used when the member list
-// overflowed): every byte becomes its plain +-1 from bit 1.
+// Word i of a lattice with every tag removed: each byte becomes the plain
+// +-1 that its bit 1 holds (bytes beyond N are kept).
+__device__ __forceinline__ uint32_t plain_word(uint32_t w, uint32_t i, uint32_t N)
+{
+    const uint32_t neg = (w >> 1) & 0x01010101u;                  // 1 where the spin is -1
+    uint32_t clean = 0x01010101u | (neg * 0xFEu);
+    if (4u * i + 4u > N) {
+        const uint32_t keep = 0xFFFFFFFFu << (8u * (N - 4u * i));
+        clean = (clean & ~keep) | (w & keep);
+    }
+    return clean;
+}
+
+// Remove the member tags from a whole lattice, by one workgroup.
 template <int WG>
 __device__ __forceinline__ void clear_tags_wg(int8_t* S, uint32_t N)
 {
@@ -390,12 +425,7 @@ __device__ __forceinline__ void clear_tags_wg(int8_t* S, uint32_t N)
     const uint32_t nw = (N + 3u) >> 2;
     for (uint32_t i = threadIdx.x; i < nw; i += WG) {
         const uint32_t w = W[i];
-        const uint32_t neg = (w >> 1) & 0x01010101u;              // 1 where the spin is -1
-        uint32_t clean = 0x01010101u | (neg * 0xFEu);
-        if (4u * i + 4u > N) {                                    // keep the padding bytes
-            const uint32_t keep = 0xFFFFFFFFu << (8u * (N - 4u * i));
-            clean = (clean & ~keep) | (w & keep);
-        }
+        const uint32_t clean = plain_word(w, i, N);
         if (clean != w) W[i] = clean;
     }
     __syncthreads();
@@ -434,8 +464,6 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
 
     int8_t* S = R->S;
     uint32_t* ov = R->ov;
-    uint32_t* members = R->members;
-    const uint32_t mcap = R->mcap;
     const Geo g = R->geo;
     const uint32_t thr = R->thr, k0 = R->k0, k1 = R->k1;
     const uint32_t t0 = R->t;
@@ -444,7 +472,11 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
     wolff_record* rec = R->rec + R->rec_count;
     int64_t M = R->M, B = R->B;
     bool b_valid = R->b_valid != 0u;
+    uint32_t t_norm = R->t_norm;
     const bool measure = R->measure != 0u;
+    // With measurement on an even-L (bipartite) lattice the bond sum follows
+    // the cluster; otherwise it is recounted over the lattice per update.
+    const bool incr = measure && (g.L & 1u) == 0u;
     uint32_t err = 0u;
     const uint32_t QC = qmask + 1u;
     uint32_t* tab = q + QC;                                       // claim table after the ring
@@ -453,20 +485,34 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
     while (done < n) {
         const uint32_t u = done;
         const uint32_t t = t0 + u;
+        if (incr && (!b_valid || t - t_norm >= TAG_EPOCHS)) {
+            // recount (B, M), check them against the tracked values, and
+            // normalise the lattice so that no byte carries this epoch's tag
+            int64_t Bm, Mm;
+            reduce_lattice_wg<WG, DIM>(S, g, red, Bm, Mm);
+            if (Mm != M) err |= ERR_MAG;
+            if (b_valid && Bm != B) err |= ERR_BOND;
+            B = Bm;
+            b_valid = true;
+            clear_tags_wg<WG>(S, g.N);
+            t_norm = t;
+        }
+        const uint32_t key = incr ? tag_key(t) : NO_TAG;
         const uint32_t s = seed_site(k0, k1, t, g.N);             // step (i)
         if (tid == 0) {
             const uint32_t a = site_addr<DIM>(g, s);
-            const int s0 = S[a];
-            S[a] = tagged_flip(s0);
+            const int s0 = (S[a] & 2) ? -1 : 1;
+            S[a] = claimed_byte(s0, key);
             q[0] = s;
             ctl->s0 = s0;
         }
         __syncthreads();
         const int s0 = ctl->s0;
+        const int8_t xb = expanded_byte(s0, key);
 
         uint32_t head = 0u, tail = 1u, ovn = 0u;                    // the paper's in / ic
         uint64_t csize = 1u;
-        uint32_t listed = 0u;                                       // members written to the list
+        uint32_t n_anti = 0u, n_inner = 0u;
         while (true) {
             uint32_t avail = tail - head;
             if (avail < (uint32_t)WG && ovn > 0u) {                 // refill the ring
@@ -482,17 +528,27 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
             const bool active = tid < nproc;
             const uint32_t j = active ? q[(head + tid) & qmask] : 0u;
             head += nproc;
-            // every member is expanded exactly once: list it for the post-pass
-            if (active && listed + tid < mcap) members[listed + tid] = j;
-            listed += nproc;
 
-            uint32_t nb[2 * DIM];
+            uint32_t self = 0u, par = 0u;
+            if (incr) {
+                // A bond inside the cluster is counted by the endpoint expanded
+                // later.  Two endpoints expanded in the same step differ in
+                // parity: the even one is marked expanded before the step's
+                // reads, the odd one after them.
+                self = site_addr_parity<DIM>(g, j, par);
+                if (active && par == 0u) S[self] = xb;
+                __syncthreads();
+            }
+            uint32_t nb[2 * DIM], sa[2 * DIM];
+            neighbours<DIM>(g, j, nb, sa);
             bool won[2 * DIM];
-            expand_site<DIM, SCOPE_WG, WG>(active, j, g, S, s0, thr, k0, k1, t, s, nb, won, tab);
+            expand_site_wg<DIM, WG>(active, j, nb, sa, S, s0, key, thr, k0, k1, t, s, won, tab,
+                                    n_anti, n_inner);
             uint32_t pos[2 * DIM];
             const uint32_t wtot = wave_compact<DIM>(won, pos);
             if (lane == 0) wave_cnt[wv] = wtot;
             __syncthreads();
+            if (incr && active && par != 0u) S[self] = xb;           // every read of the step is done
             // the step's claims are settled: empty the table for the next step
             for (uint32_t i = tid; i < tab_entries(WG); i += WG) tab[i] = TAB_EMPTY;
             uint32_t before = 0u, total = 0u;
@@ -518,45 +574,24 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
         }
 
         M -= 2 * (int64_t)s0 * (int64_t)csize;                     // exact |dM| = 2|C|
-        const bool complete = listed <= mcap;                       // the list holds the cluster
-        if (complete && measure && b_valid) {
-            // dB = -2 s0 sum_{i in C} sum_{k ~ i, k not in C} S_k: members are
-            // tagged, every untagged neighbour byte is its +-1 spin
-            int32_t qsum = 0;
-            for (uint32_t e = tid; e < listed; e += WG) {
-                uint32_t nb[2 * DIM], sa[2 * DIM];
-                neighbours<DIM>(g, members[e], nb, sa);
-#pragma unroll
-                for (int m = 0; m < 2 * DIM; ++m) {
-                    const int8_t b = S[sa[m]];
-                    qsum += is_tagged(b) ? 0 : (int32_t)b;
-                }
-            }
-            const int64_t wq = wave_sum_i64((int64_t)qsum);
-            if (lane == 0) red[wv] = wq;
+        if (incr) {
+            // Flipping C changes only the bonds between C and the rest: with
+            // n_anti of them anti-aligned and 2d|C| - n_anti - 2 n_inner
+            // aligned, dB = -4 (d |C| - n_anti - n_inner).
+            const int64_t w = wave_sum_i64((int64_t)n_anti + (int64_t)n_inner);
+            if (lane == 0) red[wv] = w;
             __syncthreads();
-            int64_t Q = 0;
+            int64_t sum = 0;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) Q += red[w];
-            B -= 2 * (int64_t)s0 * Q;
-        }
-        if (!measure || !complete) b_valid = false;
-        if (complete) {
-            __syncthreads();                                        // all tags read before clearing
-            for (uint32_t e = tid; e < listed; e += WG) S[site_addr<DIM>(g, members[e])] = (int8_t)(-s0);
-            __syncthreads();
-        } else {
-            clear_tags_wg<WG>(S, g.N);
-        }
-        if (measure && !b_valid) {
-            // a full pass: first measured update after "update only", or a
-            // cluster larger than the member list
+            for (int w2 = 0; w2 < NW; ++w2) sum += red[w2];
+            B -= 4 * ((int64_t)DIM * (int64_t)csize - sum);
+        } else if (measure) {
             int64_t Bm, Mm;
             reduce_lattice_wg<WG, DIM>(S, g, red, Bm, Mm);
             B = Bm;
-            b_valid = true;
             if (Mm != M) err |= ERR_MAG;
         }
+        b_valid = measure;
         if (tid == 0) {
             wolff_record r;
             r.bond_sum = measure ? B : (int64_t)WOLFF_NOT_MEASURED;
@@ -576,6 +611,7 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
         R->M = M;
         R->B = B;
         R->b_valid = b_valid ? 1u : 0u;
+        R->t_norm = t_norm;
         R->err |= err;
     }
 }
@@ -618,6 +654,20 @@ __global__ __launch_bounds__(WG) void batch_kernel(Rep* reps, const uint32_t* or
         __syncthreads();
         idx = __builtin_amdgcn_readfirstlane(ctl.idx);
         __syncthreads();
+    }
+}
+
+// Remove the member tags from a lattice, grid-wide (before the team path,
+// which works on plain bytes, takes over a lattice).
+__global__ void plain_kernel(int8_t* S, uint32_t N)
+{
+    uint32_t* W = reinterpret_cast<uint32_t*>(S);
+    const uint32_t nw = (N + 3u) >> 2;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += stride) {
+        const uint32_t w = W[i];
+        const uint32_t clean = plain_word(w, i, N);
+        if (clean != w) W[i] = clean;
     }
 }
 

@@ -57,6 +57,7 @@ static std::string err_message(uint32_t bits)
     std::string m;
     if (bits & wolff::ERR_MAG) m += "magnetisation recount disagrees with the cluster sizes; ";
     if (bits & wolff::ERR_TEAM_WAIT) m += "a multi-workgroup wait passed its bound; ";
+    if (bits & wolff::ERR_BOND) m += "bond-sum recount disagrees with the tracked value; ";
     if (m.empty()) m = "device error flag set";
     return m;
 }
@@ -122,15 +123,17 @@ static uint64_t host_site_addr(const Geo& g, int dim, uint64_t i)
 }
 
 // Device spins (storage order) -> host spins (site order), and back.
+// Device bytes may carry member tags; bit 1 is the sign of every byte.
 static int copy_spins_out(const Geo& g, int dim, const int8_t* dev, int8_t* host, uint64_t n)
 {
     if (!g.tiled) {
         HIP_TRY(hipMemcpy(host, dev, n, hipMemcpyDeviceToHost));
+        for (uint64_t i = 0; i < n; ++i) host[i] = (host[i] & 2) ? -1 : 1;
         return WOLFF_OK;
     }
     std::vector<int8_t> tmp(n);
     HIP_TRY(hipMemcpy(tmp.data(), dev, n, hipMemcpyDeviceToHost));
-    for (uint64_t i = 0; i < n; ++i) host[i] = tmp[host_site_addr(g, dim, i)];
+    for (uint64_t i = 0; i < n; ++i) host[i] = (tmp[host_site_addr(g, dim, i)] & 2) ? -1 : 1;
     return WOLFF_OK;
 }
 
@@ -164,13 +167,6 @@ static int check_params(int dim, int L, double J, double T, uint64_t* N)
 static constexpr uint64_t T_LIMIT = 0xFFFFFFFEull;   // t + 1 must fit the 32-bit counter word
 
 static uint64_t padded_bytes(uint64_t N) { return (N + 255u) & ~uint64_t(255); }
-
-// Member-list entries of the one-workgroup path: the whole lattice for small
-// lattices, a quarter of it otherwise (a larger cluster is measured by a full
-// lattice pass, which is then the cheaper way anyway).  The list lives after
-// the N-entry overflow stack in the same allocation.
-static uint64_t member_cap(uint64_t N) { return std::max<uint64_t>(N / 4, std::min<uint64_t>(N, 65536)); }
-static uint64_t queue_entries(uint64_t N) { return N + member_cap(N); }
 
 // -------------------------------------------------------- kernel dispatch
 static int g_num_cus = 0;
@@ -273,6 +269,7 @@ struct wolff_sim {
 
     uint64_t t = 0;
     int measure = 1;
+    bool tagged = false;                  // S may hold member tags of the one-workgroup path
     int path = WOLFF_PATH_AUTO;
     int team_wgs = 0;
     int single_wg = 256;
@@ -410,7 +407,7 @@ extern "C" int wolff_create(int dim, int L, double J, double T, uint64_t seed, w
     s->stream = s->own_stream;
     CREATE_TRY(hipMalloc(&s->S, padded_bytes(N)));
     CREATE_TRY(hipMemset(s->S, 0, padded_bytes(N)));
-    CREATE_TRY(hipMalloc(&s->ov, queue_entries(N) * sizeof(uint32_t)));
+    CREATE_TRY(hipMalloc(&s->ov, N * sizeof(uint32_t)));
     CREATE_TRY(hipMalloc(&s->d_rep, sizeof(Rep)));
     CREATE_TRY(hipMalloc(&s->d_order, sizeof(uint32_t)));
     CREATE_TRY(hipMalloc(&s->d_next, sizeof(uint32_t)));
@@ -428,8 +425,6 @@ extern "C" int wolff_create(int dim, int L, double J, double T, uint64_t seed, w
     Rep r{};
     r.S = s->S;
     r.ov = s->ov;
-    r.members = s->ov + N;
-    r.mcap = (uint32_t)member_cap(N);
     r.rec = s->d_rec;
     r.rec_count = 0;
     r.geo = s->geo;
@@ -599,6 +594,14 @@ extern "C" int wolff_run(wolff_sim* s, uint64_t n)
     const int path = resolved_path(s);
     if (path == WOLFF_PATH_TEAM) {
         if ((rc = ensure_team_queue(s))) return rc;
+        if (s->tagged) {
+            // the team path reads plain bytes: drop the one-workgroup path's tags
+            const uint32_t nw = (uint32_t)((s->N + 3) / 4);
+            hipLaunchKernelGGL(wolff::plain_kernel, dim3(std::min<uint32_t>((nw + 255) / 256, 4096)),
+                               dim3(256), 0, s->stream, s->S, (uint32_t)s->N);
+            HIP_TRY(hipGetLastError());
+            s->tagged = false;
+        }
         uint64_t u = 0;
         const uint64_t chunk = (uint64_t)s->graph_chunk;
         if (!s->profiling && chunk > 0 && n >= chunk) {
@@ -611,6 +614,7 @@ extern "C" int wolff_run(wolff_sim* s, uint64_t n)
         for (; u < n; ++u)
             if ((rc = run_team_update(s))) return rc;
     } else {
+        if (s->measure) s->tagged = true;       // measured updates leave member tags
         // one workgroup runs the updates; chunk so that one launch stays short
         const uint64_t chunk = std::max<uint64_t>(1, (1ull << 26) / std::max<uint64_t>(s->N, 1));
         for (uint64_t done = 0; done < n;) {
@@ -712,7 +716,9 @@ extern "C" int wolff_set_spins(wolff_sim* s, const int8_t* host, uint64_t n, uin
     if (rc) return rc;
     if ((rc = copy_spins_in(s->geo, s->dim, host, s->S, n))) return rc;
     r.t = (uint32_t)t;
+    r.t_norm = (uint32_t)t;
     r.rec_count = 0;
+    s->tagged = false;
     r.err = 0;
     s->t = t;
     s->rec_read = s->rec_written = 0;
@@ -855,7 +861,7 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
         b->ov_off.push_back(ov_total);
         b->rec_off.push_back(rec_total);
         s_total += padded_bytes(N);
-        ov_total += queue_entries(N);
+        ov_total += N;
         rec_total += std::max<uint64_t>(jobs[i].n_updates, 1);
     }
     b->jobs.assign(jobs, jobs + n_jobs);
@@ -880,8 +886,6 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
         r = Rep{};
         r.S = b->S + b->S_off[i];
         r.ov = b->ov + b->ov_off[i];
-        r.members = r.ov + Ns[i];
-        r.mcap = (uint32_t)member_cap(Ns[i]);
         r.rec = b->rec + b->rec_off[i];
         r.rec_count = 0;
         r.geo = make_geo(j.dim, (uint32_t)j.L);
@@ -1082,7 +1086,7 @@ struct SrvJob {
 
 uint64_t job_footprint(uint64_t N, uint64_t n_updates)
 {
-    return padded_bytes(N) + ((4 * queue_entries(N) + 255) & ~uint64_t(255)) +
+    return padded_bytes(N) + ((4 * N + 255) & ~uint64_t(255)) +
            std::max<uint64_t>(n_updates, 1) * sizeof(wolff_record) + 256;
 }
 
@@ -1210,7 +1214,7 @@ static int server_admit(wolff_server* v)
         j.block = blk;
         int8_t* S = (int8_t*)blk;
         uint32_t* ov = (uint32_t*)((char*)blk + padded_bytes(j.N));
-        wolff_record* rec = (wolff_record*)((char*)ov + ((4 * queue_entries(j.N) + 255) & ~uint64_t(255)));
+        wolff_record* rec = (wolff_record*)((char*)ov + ((4 * j.N + 255) & ~uint64_t(255)));
         HIP_TRY(hipMemsetAsync(S, 0, padded_bytes(j.N), v->stream));
         if (j.spec.start == 0) {
             hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((j.N + 255) / 256, 65536)),
@@ -1224,8 +1228,6 @@ static int server_admit(wolff_server* v)
         r = Rep{};
         r.S = S;
         r.ov = ov;
-        r.members = ov + j.N;
-        r.mcap = (uint32_t)member_cap(j.N);
         r.rec = rec;
         r.rec_count = 0;
         r.geo = make_geo(j.spec.dim, (uint32_t)j.spec.L);

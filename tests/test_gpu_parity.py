@@ -260,3 +260,42 @@ def test_measure_switch_midway():
         assert (got[100:200, 0] == binding.NOT_MEASURED).all()
         assert (got[100:200, 1:] == ref[100:200, 1:]).all()
         assert (got[200:] == ref[200:]).all(), path
+
+
+def test_path_switch_after_tagged_updates():
+    # measured one-workgroup updates leave member tags in the lattice; the
+    # team path must see plain spins, and both must stay on the oracle's
+    # trajectory across several epochs of tags (more than 32 updates)
+    dim, L, T, seed = 2, 48, TC2, 83
+    ref, Sref = oracle_series(dim, L, T, seed, 230)
+    with binding.Simulation(dim, L, 1.0, T, seed) as sim:
+        sim.set_path(binding.PATH_SINGLE)
+        sim.run(70)
+        sim.set_path(binding.PATH_TEAM, 8)
+        sim.run(50)
+        sim.set_path(binding.PATH_SINGLE)
+        sim.run(40)
+        S_mid = sim.spins()
+        sim.set_measure(False)
+        sim.run(30)
+        sim.set_measure(True)
+        sim.set_path(binding.PATH_TEAM, 8)
+        sim.run(40)
+        got = as_array(sim.observables())
+        S = sim.spins()
+    assert set(np.unique(S_mid)) <= {-1, 1}
+    assert (got[:160] == ref[:160]).all()
+    assert (got[160:190, 1:] == ref[160:190, 1:]).all()
+    assert (got[190:] == ref[190:]).all()
+    assert (S == Sref).all()
+
+
+@pytest.mark.parametrize("dim,L,T", [(2, 64, TC2), (3, 16, T3), (2, 32, 1.5), (3, 12, 3.0)])
+def test_long_measured_run_single(dim, L, T):
+    # many epochs of member tags: the running bond sum is cross-checked
+    # against a lattice recount every 32 updates inside the kernel
+    n = 700
+    got, S, _ = gpu_series(dim, L, T, 97, n, binding.PATH_SINGLE)
+    ref, Sref = oracle_series(dim, L, T, 97, n)
+    assert (got == ref).all()
+    assert (S == Sref).all()
