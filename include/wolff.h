@@ -81,9 +81,9 @@ typedef struct wolff_sim wolff_sim;
 
 /* Create a lattice of L^dim spins, iid +-1 from `seed` (update index t = 0).
  * dim in {2, 3}; L >= 2; L^dim < 2^32; J > 0 and T > 0 finite.
- * Allocates about 6 bytes per site of device memory (spins, the overflow
- * stack and member list of the one-workgroup path), plus 8 bytes per site
- * for the multi-workgroup queue on the first team-path run.
+ * Allocates about 5 bytes per site of device memory (spins and the overflow
+ * stack of the one-workgroup path), plus 8 bytes per site for the
+ * multi-workgroup queue on the first team-path run.
  * Synchronises before returning.  *out is set only on success. */
 int wolff_create(int dim, int L, double J, double T, uint64_t seed, wolff_sim **out);
 
@@ -96,7 +96,8 @@ int wolff_run(wolff_sim *s, uint64_t n_updates);
 
 /* Wait for the stream, then move up to `cap` pending records, oldest first,
  * into out[]; *n_out receives the number moved.  Returns WOLFF_ESTATE if a
- * device-side consistency check (the magnetisation recount) failed. */
+ * device-side consistency check (a recount of the magnetisation or of the
+ * bond sum disagreeing with the tracked value) failed. */
 int wolff_observables(wolff_sim *s, wolff_record *out, uint64_t cap, uint64_t *n_out);
 
 /* Wait for all work enqueued on the handle's stream. */
@@ -113,10 +114,11 @@ int wolff_get_spins(wolff_sim *s, int8_t *host, uint64_t n);
  * are dropped and the observables recomputed. */
 int wolff_set_spins(wolff_sim *s, const int8_t *host, uint64_t n, uint64_t t);
 
-/* 1: bond_sum after every update (the paper's "+ measurement"): the
- * one-workgroup path updates it exactly from the cluster's boundary (a pass
- * over the members' neighbours), the team path and large clusters recount it
- * over the lattice; 0: "update only", bond_sum = WOLFF_NOT_MEASURED.
+/* 1: bond_sum after every update (the paper's "+ measurement"): for even L
+ * the one-workgroup path updates it exactly from counts taken while the
+ * cluster grows (and recounts it over the lattice every 32 updates as a
+ * check); the team path and odd L recount it over the lattice after every
+ * update; 0: "update only", bond_sum = WOLFF_NOT_MEASURED.
  * mag and csize are exact in both modes.  Default 1. */
 int wolff_set_measure(wolff_sim *s, int on);
 
@@ -219,8 +221,8 @@ int wolff_batch_last_ms(wolff_batch *b, double *ms);
  * resident job in time-bounded quanta, each one persistent launch of the
  * batched kernel (continuous batching).  Jobs are admitted first-in
  * first-out while a workgroup slot and their HBM footprint are free
- * (footprint = spins + overflow stack + member list + records: about
- * 6 N + 24 n_updates bytes); a job submitted while others run joins the next quantum, so its
+ * (footprint = spins + overflow stack + records: about 5 N + 24 n_updates
+ * bytes); a job submitted while others run joins the next quantum, so its
  * updates overlap with theirs on the device.  Every job's records are
  * exactly those of the same job run alone (the random stream is keyed by the
  * job's own seed and update index, never by its neighbours in the batch).
