@@ -23,32 +23,27 @@ constexpr int SCOPE_AGENT = __HIP_MEMORY_SCOPE_AGENT;
 // still holds s0, and claim the neighbours whose bond is active.
 //   +mu neighbour: bond (j, mu)          -> word mu of philox((j, t, s, 0))
 //   -mu neighbour: bond (j - e_mu, mu)   -> word mu of philox((j - e_mu, t, s, 0))
-// One Philox block serves all +mu bonds of j.  Random words are only drawn
-// for eligible neighbours; the cluster does not depend on which thread
-// claims a site first, so no ordering between threads is needed.
+// One Philox block serves all +mu bonds of j.  The cluster does not depend
+// on which thread claims a site first, so no ordering between threads is
+// needed.  Both paths draw every bond word of j while the neighbour loads
+// are in flight: more arithmetic than drawing for eligible neighbours only,
+// but a shorter step, and the step's latency bounds the growth.
+
+// Random words of the bonds of j: the +mu bonds from one block keyed by j,
+// each -mu bond from the block keyed by its base site j - e_mu.
 template <int DIM>
-__device__ __forceinline__ void active_bonds(const bool el[2 * DIM], uint32_t j,
-                                             const uint32_t nb[2 * DIM], uint32_t thr, uint32_t k0,
-                                             uint32_t k1, uint32_t t, uint32_t s, bool act[2 * DIM])
+__device__ __forceinline__ void bond_words(uint32_t j, const uint32_t nb[2 * DIM], uint32_t k0,
+                                           uint32_t k1, uint32_t t, uint32_t s,
+                                           uint32_t rp[3], uint32_t rm[3])
 {
-    uint32_t rp[3] = {0u, 0u, 0u};
-    const bool need_plus = el[0] || el[2] || (DIM == 3 && el[2 * (DIM - 1)]);
-    if (need_plus) {
-        const U4 r = philox(j, t, s, DOMAIN_BOND, k0, k1);
-        rp[0] = r.x;
-        rp[1] = r.y;
-        rp[2] = r.z;
-    }
+    const U4 r = philox(j, t, s, DOMAIN_BOND, k0, k1);
+    rp[0] = r.x;
+    rp[1] = r.y;
+    rp[2] = r.z;
 #pragma unroll
     for (int mu = 0; mu < DIM; ++mu) {
-        act[2 * mu] = el[2 * mu] && rp[mu] < thr;
-        bool a = false;
-        if (el[2 * mu + 1]) {
-            const U4 r = philox(nb[2 * mu + 1], t, s, DOMAIN_BOND, k0, k1);
-            const uint32_t w = (mu == 0) ? r.x : (mu == 1) ? r.y : r.z;
-            a = w < thr;
-        }
-        act[2 * mu + 1] = a;
+        const U4 q = philox(nb[2 * mu + 1], t, s, DOMAIN_BOND, k0, k1);
+        rm[mu] = (mu == 0) ? q.x : (mu == 1) ? q.y : q.z;
     }
 }
 
@@ -62,13 +57,16 @@ __device__ __forceinline__ void expand_site(bool active, uint32_t j, const Geo& 
     if (!active) j = 0u;
     uint32_t sa[2 * DIM];
     neighbours<DIM>(g, j, nb, sa);
-    bool el[2 * DIM];
+    int b[2 * DIM];
 #pragma unroll
-    for (int m = 0; m < 2 * DIM; ++m) el[m] = active && (int)S[sa[m]] == s0;
-    bool act[2 * DIM];
-    active_bonds<DIM>(el, j, nb, thr, k0, k1, t, s, act);
+    for (int m = 0; m < 2 * DIM; ++m) b[m] = S[sa[m]];
+    uint32_t rp[3], rm[3];
+    bond_words<DIM>(j, nb, k0, k1, t, s, rp, rm);
 #pragma unroll
-    for (int m = 0; m < 2 * DIM; ++m) won[m] = act[m] && claim<SCOPE>(S, sa[m], s0);
+    for (int m = 0; m < 2 * DIM; ++m) {
+        const uint32_t r = (m & 1) ? rm[m / 2] : rp[m / 2];
+        won[m] = active && b[m] == s0 && r < thr && claim<SCOPE>(S, sa[m], s0);
+    }
 }
 
 // Claim table of the one-workgroup path.  Only one workgroup touches the
@@ -88,18 +86,37 @@ __host__ __device__ constexpr uint32_t tab_shift(int wg)
     return wg == 64 ? 23u : wg == 128 ? 22u : wg == 256 ? 21u : wg == 512 ? 20u : 19u;
 }
 
-// true: this thread won site a for the step.
-template <int WG>
-__device__ __forceinline__ bool table_claim(uint32_t* tab, uint32_t a)
+// won[m]: this thread won site a[m] for the step.  The first probes of all
+// slots go out together (one LDS round trip); a slot whose first probe met
+// another key keeps probing linearly.  Two slots of one thread holding the
+// same site (L = 2) are settled in slot order: the second finds the first.
+template <int WG, int DIM>
+__device__ __forceinline__ void table_claims(uint32_t* tab, const uint32_t a[2 * DIM],
+                                             const bool act[2 * DIM], bool won[2 * DIM])
 {
-    uint32_t h = (a * 0x9E3779B1u) >> tab_shift(WG);
-    for (uint32_t p = 0; p < tab_entries(WG); ++p) {
-        const uint32_t prev = atomicCAS(&tab[h], TAB_EMPTY, a);
-        if (prev == TAB_EMPTY) return true;
-        if (prev == a) return false;
-        h = (h + 1u) & (tab_entries(WG) - 1u);
+    uint32_t h[2 * DIM], prev[2 * DIM];
+#pragma unroll
+    for (int m = 0; m < 2 * DIM; ++m) {
+        h[m] = (a[m] * 0x9E3779B1u) >> tab_shift(WG);
+        prev[m] = act[m] ? atomicCAS(&tab[h[m]], TAB_EMPTY, a[m]) : a[m];
     }
-    return false;   // unreachable: the table always has an empty slot
+#pragma unroll
+    for (int m = 0; m < 2 * DIM; ++m) {
+        bool w = prev[m] == TAB_EMPTY;
+        if (act[m] && prev[m] != TAB_EMPTY && prev[m] != a[m]) {
+            uint32_t hh = h[m];
+            for (uint32_t p = 1; p < tab_entries(WG); ++p) {   // ends early: the table is never full
+                hh = (hh + 1u) & (tab_entries(WG) - 1u);
+                const uint32_t pv = atomicCAS(&tab[hh], TAB_EMPTY, a[m]);
+                if (pv == TAB_EMPTY) {
+                    w = true;
+                    break;
+                }
+                if (pv == a[m]) break;
+            }
+        }
+        won[m] = w;
+    }
 }
 
 // One-workgroup path.  `key` is the tag of the update (NO_TAG: plain bytes).
@@ -116,23 +133,25 @@ __device__ __forceinline__ void expand_site_wg(bool active, uint32_t j, const ui
                                                uint32_t& n_anti, uint32_t& n_inner)
 {
     const uint32_t neg0 = s0 < 0 ? 2u : 0u;            // bit 1 of an s0 byte
-    bool el[2 * DIM];
+    uint32_t b[2 * DIM];
+#pragma unroll
+    for (int m = 0; m < 2 * DIM; ++m) b[m] = (uint8_t)S[sa[m]];
+    uint32_t rp[3], rm[3];
+    bond_words<DIM>(j, nb, k0, k1, t, s, rp, rm);
+    bool act[2 * DIM];
 #pragma unroll
     for (int m = 0; m < 2 * DIM; ++m) {
-        const uint32_t b = (uint8_t)S[sa[m]];
-        const bool same = (b & 2u) == neg0;
-        el[m] = active && same;
-        n_anti += (active && !same && !is_member(b, key)) ? 1u : 0u;
-        n_inner += (active && is_expanded(b, key)) ? 1u : 0u;
+        const bool same = (b[m] & 2u) == neg0;
+        const uint32_t r = (m & 1) ? rm[m / 2] : rp[m / 2];
+        act[m] = active && same && r < thr;
+        n_anti += (active && !same && !is_member(b[m], key)) ? 1u : 0u;
+        n_inner += (active && is_expanded(b[m], key)) ? 1u : 0u;
     }
-    bool act[2 * DIM];
-    active_bonds<DIM>(el, j, nb, thr, k0, k1, t, s, act);
+    table_claims<WG, DIM>(tab, sa, act, won);
     const int8_t cb = claimed_byte(s0, key);
 #pragma unroll
-    for (int m = 0; m < 2 * DIM; ++m) {
-        won[m] = act[m] && table_claim<WG>(tab, sa[m]);
+    for (int m = 0; m < 2 * DIM; ++m)
         if (won[m]) S[sa[m]] = cb;
-    }
 }
 
 // Wave-level compaction of the claimed sites: one ballot per neighbour slot,
