@@ -49,9 +49,9 @@ def kernel_source_sha() -> str:
     return sha()
 
 
-def counter_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources (else None)."""
+def counter_summary(kernel: str, workload: str):
+    """A committed rocprofv3 counter summary, if it was taken on the current
+    kernel sources (else None)."""
     path = os.path.join(ROOT, "profiles", "counters_%s_%s.json" % (kernel, workload))
     if not os.path.exists(path):
         return None
@@ -59,7 +59,13 @@ def counter_traffic(kernel: str, workload: str):
         d = json.load(f)
     if d.get("kernel_source_sha") != kernel_source_sha():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d
+
+
+def counter_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the counter summary (else None)."""
+    d = counter_summary(kernel, workload)
+    return None if d is None else d.get("hbm_bytes_per_launch")
 
 
 def ordered_start(n_sites: int) -> np.ndarray:
@@ -218,12 +224,11 @@ def profile_only(args, binding, workloads):
         r = plain_leg(binding, 2, 4096, workloads.TC_2D, 2, args.warmup, args.steps)
     elif leg == "plain3d":
         r = plain_leg(binding, 3, 256, workloads.T_3D, 3, args.warmup, args.steps)
-    elif leg == "batch2d":
-        r = batch_leg(binding, workloads, 2, 4096, args.batch_replicas, args.warmup,
-                      args.batch_steps, wg=256, q=2048)
-    elif leg == "batch3d":
-        r = batch_leg(binding, workloads, 3, 256, args.batch_replicas, args.warmup,
-                      args.batch_steps, wg=256, q=2048)
+    elif leg in ("batch2d", "batch3d"):
+        wg, q = (int(v) for v in args.tiles.split(","))
+        dim, L = (2, 4096) if leg == "batch2d" else (3, 256)
+        r = batch_leg(binding, workloads, dim, L, args.batch_replicas, args.warmup,
+                      args.batch_steps, wg=wg, q=q)
     else:
         raise SystemExit("unknown leg %s" % leg)
     r = {k: v for k, v in r.items() if k not in ("records", "checkpoint")}
@@ -237,10 +242,13 @@ def main():
     ap.add_argument("--steps", type=int, default=2000, help="timed updates of the headline leg")
     ap.add_argument("--warmup", type=int, default=1000, help="thermalisation updates")
     ap.add_argument("--legs", default="plain2d,plain3d,batch2d,batch3d,serve")
-    ap.add_argument("--batch-replicas", type=int, default=1024)
+    ap.add_argument("--batch-replicas", type=int, default=1536)
     ap.add_argument("--batch-steps", type=int, default=8)
     ap.add_argument("--batch-warmup", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--tiles", default="512,2048",
+                    help="workgroup size, LDS ring entries of a profiled batch leg (the full "
+                         "benchmark takes them from the autotuner)")
     ap.add_argument("--profile-leg", default=None,
                     help="run only this leg (plain2d, plain3d, batch2d, batch3d, copy) for a "
                          "profiler; prints that leg's numbers instead of the benchmark line")
@@ -274,6 +282,9 @@ def main():
                                             args.batch_warmup, args.batch_steps)
         extra["batch_2d_L4096"]["vs_plain"] = (extra["batch_2d_L4096"]["added_per_s"]
                                                / main_leg["added_per_s"])
+        c = counter_summary("batch_kernel", "batch_2d_L4096x%d" % args.batch_replicas)
+        extra["batch_2d_L4096"]["traffic_bytes_per_added_spin"] = (
+            None if c is None else c.get("hbm_bytes_per_added_spin"))
     if "batch3d" in legs:
         extra["batch_3d_L256"] = batch_leg(binding, workloads, 3, 256, args.batch_replicas,
                                            10 * args.batch_warmup, 5 * args.batch_steps)
