@@ -1,13 +1,16 @@
 """Benchmark of the Wolff single-cluster hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs plain2d,plain3d,batch2d,batch3d]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs plain2d,plain3d,...]
 
 A step is one Wolff update of the whole hot path (seed draw, frontier growth
 with bond activation, claim-and-flip, E/M measurement, record) on the
 workload's lattice.  The headline workload is the square lattice L = 4096 at
 T_c = 2/ln(1+sqrt 2) through the plain one-lattice launch path; the other
-legs (simple-cubic L = 256, and the batched persistent form on both) are
-reported under "extra".  Inputs are synthetic (seeded, no dataset).
+legs are reported under "extra": simple-cubic L = 256, both plain lattices
+in "update only" mode, the L = 32 latency case with the oracle on all of it,
+the batched persistent form on 1536 replicas of each lattice, the mixed
+replica set, the serving stream, and a device-copy bandwidth for the
+roofline.  Inputs are synthetic (seeded, no dataset).
 
 Prints ONE JSON line.  `value` is added spins per second (sum of cluster
 sizes over the timed updates / wall time between synchronisations).
@@ -72,11 +75,11 @@ def ordered_start(n_sites: int) -> np.ndarray:
     return np.ones(n_sites, dtype=np.int8)
 
 
-def plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered=True):
+def plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered=True, measure=True):
     """Plain one-lattice path: warmup updates, then `steps` timed updates."""
     import torch
     sim = binding.Simulation(dim, L, 1.0, T, seed)
-    sim.set_measure(True)
+    sim.set_measure(measure)
     if start_ordered:
         sim.set_spins(ordered_start(L ** dim), 0)
     t0 = time.time()
@@ -106,6 +109,7 @@ def plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered=True):
            grow_ms / max(prof["grow_launches"], 1)))
     return {
         "dim": dim, "L": L, "T": T, "seed": seed, "warmup": warmup, "steps": steps,
+        "measurement": bool(measure),
         "wall_s": wall, "added": added, "added_per_s": added / wall,
         "updates_per_s": steps / wall, "mean_csize": added / max(steps, 1),
         "grow_ms": grow_ms, "grow_launches": prof["grow_launches"],
@@ -157,6 +161,81 @@ def batch_leg(binding, workloads, dim, L, n_rep, warmup, steps, wg=None, q=None)
         "kernel_frac_of_hbm_peak": BYTES_PER_ADDED[dim] * added / kernel_s / 1e9 / HBM_PEAK_GBS,
         "tiles": "autotuner" if tuned else "fixed",
     }
+
+
+def c1_leg(binding, workloads):
+    """C1: square lattice L=32 at T_c from the random start, 10^4 measured
+    updates; latency per update on the GPU, and the oracle on all of it
+    (its records must equal the GPU's)."""
+    import oracle
+    c = workloads.C1
+    n = c["n_meas"]
+    with binding.Simulation(c["dim"], c["L"], 1.0, c["T"], c["seed"]) as sim:
+        sim.run(1)
+        sim.synchronize()
+        sim.observables()
+        a = time.perf_counter()
+        sim.run(n)
+        sim.synchronize()
+        wall = time.perf_counter() - a
+        rec = sim.observables()
+        path = int(sim.info().path)
+    S = oracle.init_spins(c["dim"], c["L"], c["seed"])
+    thr = oracle.threshold(1.0, c["T"])
+    oracle.run(c["dim"], c["L"], thr, c["seed"], 0, 1, S)
+    a = time.perf_counter()
+    ref = oracle.run(c["dim"], c["L"], thr, c["seed"], 1, n, S)
+    cpu_s = time.perf_counter() - a
+    got = np.stack([rec["bond_sum"], rec["mag"], rec["csize"]], axis=1)
+    added = int(rec["csize"].sum())
+    log("C1: %d updates, %.2f us/update on the GPU, oracle %.2f us/update, records match: %s"
+        % (n, 1e6 * wall / n, 1e6 * cpu_s / n, bool((got == ref).all())))
+    return {"updates": n, "gpu_us_per_update": 1e6 * wall / n, "gpu_added_per_s": added / wall,
+            "oracle_us_per_update": 1e6 * cpu_s / n, "oracle_added_per_s": added / cpu_s,
+            "oracle_cores": 1, "records_match_oracle": bool((got == ref).all()),
+            "mean_csize": added / n, "path": path}
+
+
+def c4_leg(binding, workloads, n_updates):
+    """C4: the mixed replica set (256 square lattices L in {64..1024},
+    T in [2.0, 2.6]; 64 simple-cubic L in {32, 64, 128}, T in [4.3, 4.7]),
+    random starts, n_updates each in one persistent launch with measurement."""
+    jobs = workloads.c4_jobs(n_updates)
+    from paper_1110_0899_amd import autotune
+    tuned = autotune.tune(workloads.c4_jobs(8), warm=2, timed=4, start=0, log=log)
+    b = binding.Batch(jobs, start=0)
+    b.set_tiles(tuned["wg"], tuned["queue_entries"])
+    b.set_measure(True)
+    a = time.perf_counter()
+    b.run()
+    ms = b.last_ms()
+    wall = time.perf_counter() - a
+    added = sum(int(b.records(i)["csize"].sum()) for i in range(len(jobs)))
+    b.close()
+    log("C4: %d replicas x %d updates, makespan %.2f s (kernel %.2f s), %.3e added/s"
+        % (len(jobs), n_updates, wall, ms * 1e-3, added / wall))
+    return {"replicas": len(jobs), "updates_each": n_updates, "makespan_s": wall,
+            "kernel_s": ms * 1e-3, "added": added, "added_per_s": added / wall,
+            "cluster_updates_per_s": len(jobs) * n_updates / wall,
+            "wg": tuned["wg"], "queue_entries": tuned["queue_entries"]}
+
+
+def copy_peak_gbs(reps=5):
+    """Device-to-device copy bandwidth (read + write bytes / time), 2 GiB."""
+    import torch
+    n = 2 << 30
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * n * reps / el / 1e9
 
 
 def serve_leg(workloads, quantum_ms=5.0, n_jobs=2000, max_wall_s=20.0):
@@ -241,7 +320,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000, help="timed updates of the headline leg")
     ap.add_argument("--warmup", type=int, default=1000, help="thermalisation updates")
-    ap.add_argument("--legs", default="plain2d,plain3d,batch2d,batch3d,serve")
+    ap.add_argument("--legs", default="plain2d,plain3d,updateonly,c1,batch2d,batch3d,c4,serve")
+    ap.add_argument("--c4-updates", type=int, default=10000,
+                    help="updates per replica of the mixed C4 batch")
     ap.add_argument("--batch-replicas", type=int, default=1536)
     ap.add_argument("--batch-steps", type=int, default=8)
     ap.add_argument("--batch-warmup", type=int, default=100)
@@ -292,8 +373,28 @@ def main():
             extra["batch_3d_L256"]["vs_plain"] = (extra["batch_3d_L256"]["added_per_s"]
                                                   / extra["plain_3d_L256"]["added_per_s"])
 
+    if "updateonly" in legs:
+        # the paper's Table 1 reports both modes: "update only" and "+ measurement"
+        u2 = plain_leg(binding, 2, 4096, workloads.TC_2D, 2, args.warmup, args.steps,
+                       measure=False)
+        extra["plain_2d_L4096_update_only"] = {k: v for k, v in u2.items()
+                                               if k not in ("records", "checkpoint")}
+        if "plain3d" in legs:
+            u3 = plain_leg(binding, 3, 256, workloads.T_3D, 3, 3 * args.warmup, 5 * args.steps,
+                           measure=False)
+            extra["plain_3d_L256_update_only"] = {k: v for k, v in u3.items()
+                                                  if k not in ("records", "checkpoint")}
+    if "c1" in legs:
+        extra["c1_2d_L32"] = c1_leg(binding, workloads)
+    if "c4" in legs:
+        extra["c4_mixed_batch"] = c4_leg(binding, workloads, args.c4_updates)
     if "serve" in legs:
         extra["serve_stream"] = serve_leg(workloads)
+    copy_gbs = copy_peak_gbs()
+    log("device copy: %.0f GB/s" % copy_gbs)
+    for leg in extra.values():
+        if isinstance(leg, dict) and "kernel_GBs_algorithmic" in leg:
+            leg["kernel_frac_of_measured_copy"] = leg["kernel_GBs_algorithmic"] / copy_gbs
 
     achieved = main_leg["grow_GBs_algorithmic"]
     traffic = counter_traffic("team_kernel", "2d_L4096")
@@ -327,6 +428,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "measured_copy_GBs": copy_gbs,
+            "frac_of_measured_copy": achieved / copy_gbs,
             "bytes_per_added_spin": BYTES_PER_ADDED[2],
             "launches": main_leg["grow_launches"],
             "avg_launch_ms": main_leg["grow_ms"] / max(main_leg["grow_launches"], 1),
