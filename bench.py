@@ -75,8 +75,11 @@ def ordered_start(n_sites: int) -> np.ndarray:
     return np.ones(n_sites, dtype=np.int8)
 
 
-def plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered=True, measure=True):
-    """Plain one-lattice path: warmup updates, then `steps` timed updates."""
+def plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered=True, measure=True,
+              warm_sweeps=0.0):
+    """Plain one-lattice path: warmup updates (and, with warm_sweeps, more
+    until the flipped spins add up to that many lattice sweeps), then
+    `steps` timed updates."""
     import torch
     sim = binding.Simulation(dim, L, 1.0, T, seed)
     sim.set_measure(measure)
@@ -86,6 +89,24 @@ def plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered=True, measu
     sim.run(warmup)
     sim.synchronize()
     sim.observables()
+    if warm_sweeps:
+        # small clusters: thermalise "update only" until the flipped spins add
+        # up to warm_sweeps lattices
+        sim.set_measure(False)
+        flipped, last = 0, time.time()
+        while flipped < warm_sweeps * L ** dim and warmup < 20_000_000:
+            sim.run(50_000)
+            flipped += int(sim.observables()["csize"].sum())
+            warmup += 50_000
+            if time.time() - last > 10.0:
+                last = time.time()
+                log("%dD L=%d T=%.4f: %d updates, %.2f sweeps flipped"
+                    % (dim, L, T, warmup, flipped / L ** dim))
+        sim.set_measure(measure)
+        sim.run(100)
+        sim.synchronize()
+        sim.observables()
+        warmup += 100
     log("%dD L=%d: %d warmup updates in %.1f s" % (dim, L, warmup, time.time() - t0))
     checkpoint = sim.spins()
     t_ckpt = sim.info().t
@@ -220,6 +241,62 @@ def c4_leg(binding, workloads, n_updates):
             "wg": tuned["wg"], "queue_entries": tuned["queue_entries"]}
 
 
+PAPER_TABLES = {  # ms per update at T_c on the paper's GTX 285 / one Xeon W3520 core (Tables 1-2):
+    # (GPU update only, GPU + measurement, CPU update only, CPU + measurement)
+    (2, 512): (7.634, 7.677, 4.151, 4.913), (2, 1024): (15.80, 16.10, 20.97, 24.19),
+    (2, 2048): (33.02, 34.50, 87.59, 100.9), (2, 4096): (81.37, 83.95, 412.0, 470.9),
+    (3, 64): (1.176, 1.378, 1.170, 1.947), (3, 128): (2.801, 3.483, 9.785, 15.76),
+    (3, 256): (13.04, 17.45, 97.47, 137.9),
+}
+
+
+def sweep_point(binding, dim, L, T, seed, warmup, steps, start_ordered, cpu_seconds):
+    """GPU ms per update in both modes (the same updates: state and random
+    stream do not depend on the mode) and the oracle's ms per update with
+    measurement, replayed from the GPU's state."""
+    sweeps = 0.0 if start_ordered else 2.0
+    m = plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered, measure=True,
+                  warm_sweeps=sweeps)
+    u = plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered, measure=False,
+                  warm_sweeps=sweeps)
+    cpu = cpu_baseline(m, cpu_seconds)
+    gpu_ms = 1e3 * m["wall_s"] / steps
+    cpu_ms = 1e3 * cpu["seconds"] / max(cpu["updates"], 1)
+    return {"dim": dim, "L": L, "T": T, "start": "ordered" if start_ordered else "random",
+            "warmup": m["warmup"], "steps": steps, "mean_csize": m["mean_csize"],
+            "gpu_ms_update_only": 1e3 * u["wall_s"] / steps, "gpu_ms_measure": gpu_ms,
+            "cpu_ms_measure": cpu_ms, "cpu_updates": cpu["updates"],
+            "cpu_records_match": cpu["records_match_gpu"], "speedup_measure": cpu_ms / gpu_ms,
+            "path": m["path"]}
+
+
+def sizes_leg(binding, workloads, cpu_seconds):
+    """The paper's size sweep (Tables 1-2) at T_c."""
+    rows = []
+    for dim, Ls, T, warm, steps in ((2, (512, 1024, 2048, 4096), workloads.TC_2D, 300, 300),
+                                    (3, (64, 128, 256), workloads.T_3D, 1000, 1000)):
+        for L in Ls:
+            r = sweep_point(binding, dim, L, T, 2 if dim == 2 else 3, warm, steps, True, cpu_seconds)
+            r["paper_ms"] = dict(zip(("gpu_update_only", "gpu_measure", "cpu_update_only",
+                                      "cpu_measure"), PAPER_TABLES[(dim, L)]))
+            rows.append(r)
+    return rows
+
+
+def temps_leg(binding, workloads, cpu_seconds):
+    """The paper's temperature sweep (Fig. 1): 2D L=4096 and 3D L=256 at
+    T/T_c from 0.9 to 1.1; ordered start at and below T_c; above T_c a
+    random start thermalised until the flipped spins add up to two lattices."""
+    rows = []
+    for dim, L, Tc, warm, steps in ((2, 4096, workloads.TC_2D, 100, 100),
+                                    (3, 256, workloads.T_3D, 300, 300)):
+        for f in (0.9, 0.95, 1.0, 1.05, 1.1):
+            rows.append(sweep_point(binding, dim, L, Tc * f, 2 if dim == 2 else 3, warm, steps,
+                                    f <= 1.0, cpu_seconds))
+            rows[-1]["T_over_Tc"] = f
+    return rows
+
+
 def copy_peak_gbs(reps=5):
     """Device-to-device copy bandwidth (read + write bytes / time), 2 GiB."""
     import torch
@@ -327,6 +404,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=8)
     ap.add_argument("--batch-warmup", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--sweep-cpu-seconds", type=float, default=4.0,
+                    help="oracle time per point of the sweeps (legs sizes, temps; run without "
+                         "plain2d, they print their own JSON line)")
     ap.add_argument("--tiles", default="512,2048",
                     help="workgroup size, LDS ring entries of a profiled batch leg (the full "
                          "benchmark takes them from the autotuner)")
@@ -350,6 +430,16 @@ def main():
 
     if args.profile_leg:
         profile_only(args, binding, workloads)
+        return
+
+    if "plain2d" not in legs:
+        # studies only (no headline): the paper's size and temperature sweeps
+        out = {}
+        if "sizes" in legs:
+            out["sizes"] = sizes_leg(binding, workloads, args.sweep_cpu_seconds)
+        if "temps" in legs:
+            out["temps"] = temps_leg(binding, workloads, args.sweep_cpu_seconds)
+        print(json.dumps(out), flush=True)
         return
 
     main_leg = plain_leg(binding, 2, 4096, workloads.TC_2D, 2, args.warmup, args.steps)

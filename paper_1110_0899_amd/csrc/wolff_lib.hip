@@ -271,6 +271,7 @@ struct wolff_sim {
     int measure = 1;
     bool tagged = false;                  // S may hold member tags of the one-workgroup path
     int path = WOLFF_PATH_AUTO;
+    double csize_mean = -1.0;             // mean |C| of the records last returned (-1: none yet)
     int team_wgs = 0;
     int single_wg = 256;
     int single_q = 2048;
@@ -286,10 +287,19 @@ struct wolff_sim {
     uint64_t grow_n = 0, meas_n = 0;
 };
 
+// Mean cluster size below which a large lattice runs "update only" updates
+// on one workgroup: a few thousand sites are a handful of growth steps, and
+// one launch for many updates beats three launches (seed, team, recount)
+// per update.  With measurement the team path stays: there the one
+// workgroup's periodic lattice recount would cost more than the launches.
+static constexpr double SMALL_CLUSTER = 16384.0;
+
 static int resolved_path(const wolff_sim* s)
 {
     if (s->path != WOLFF_PATH_AUTO) return s->path;
-    return (s->N >= (1ull << 20)) ? WOLFF_PATH_TEAM : WOLFF_PATH_SINGLE;
+    if (s->N < (1ull << 20)) return WOLFF_PATH_SINGLE;
+    return (!s->measure && s->csize_mean >= 0.0 && s->csize_mean < SMALL_CLUSTER)
+               ? WOLFF_PATH_SINGLE : WOLFF_PATH_TEAM;
 }
 
 static int team_size(const wolff_sim* s)
@@ -616,7 +626,11 @@ extern "C" int wolff_run(wolff_sim* s, uint64_t n)
     } else {
         if (s->measure) s->tagged = true;       // measured updates leave member tags
         // one workgroup runs the updates; chunk so that one launch stays short
-        const uint64_t chunk = std::max<uint64_t>(1, (1ull << 26) / std::max<uint64_t>(s->N, 1));
+        // (about 2^26 sites of work: the expected cluster, plus the lattice
+        // recount every 32 measured updates), at most 65536 updates
+        const double cl = s->csize_mean >= 0.0 ? s->csize_mean : (double)s->N;
+        const double work = cl + (s->measure ? (double)s->N / 32.0 : 0.0) + 64.0;
+        const uint64_t chunk = (uint64_t)std::max(1.0, std::min(65536.0, (double)(1ull << 26) / work));
         for (uint64_t done = 0; done < n;) {
             const uint32_t m = (uint32_t)std::min<uint64_t>(chunk, n - done);
             EventPair ev{};
@@ -653,9 +667,13 @@ extern "C" int wolff_observables(wolff_sim* s, wolff_record* out, uint64_t cap, 
     if (rc) return rc;
     const uint64_t live = s->rec_written - s->rec_read;
     const uint64_t k = std::min(cap, live);
-    if (k)
+    if (k) {
         HIP_TRY(hipMemcpy(out, s->d_rec + s->rec_read, k * sizeof(wolff_record),
                           hipMemcpyDeviceToHost));
+        double sum = 0.0;
+        for (uint64_t i = 0; i < k; ++i) sum += (double)out[i].csize;
+        s->csize_mean = sum / (double)k;      // steers WOLFF_PATH_AUTO
+    }
     s->rec_read += k;
     if (n_out) *n_out = k;
     bool push = false;
@@ -719,6 +737,7 @@ extern "C" int wolff_set_spins(wolff_sim* s, const int8_t* host, uint64_t n, uin
     r.t_norm = (uint32_t)t;
     r.rec_count = 0;
     s->tagged = false;
+    s->csize_mean = -1.0;
     r.err = 0;
     s->t = t;
     s->rec_read = s->rec_written = 0;

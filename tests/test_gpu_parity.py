@@ -299,3 +299,29 @@ def test_long_measured_run_single(dim, L, T):
     ref, Sref = oracle_series(dim, L, T, 97, n)
     assert (got == ref).all()
     assert (S == Sref).all()
+
+
+def test_auto_path_follows_cluster_size():
+    # a large lattice above T_c, "update only": the first run uses the team
+    # path; once the returned records show small clusters, AUTO moves to one
+    # workgroup, and back to the team path when measurement is switched on;
+    # the records stay on the oracle's trajectory throughout
+    dim, L, T, seed = 2, 1024, 3.2, 29
+    ref, Sref = oracle_series(dim, L, T, seed, 90)
+    with binding.Simulation(dim, L, 1.0, T, seed) as sim:
+        sim.set_measure(False)
+        assert sim.info().path == binding.PATH_TEAM
+        sim.run(30)
+        got1 = as_array(sim.observables())
+        assert sim.info().path == binding.PATH_SINGLE
+        sim.run(30)
+        got2 = as_array(sim.observables())
+        sim.set_measure(True)
+        assert sim.info().path == binding.PATH_TEAM
+        sim.run(30)
+        got3 = as_array(sim.observables())
+        S = sim.spins()
+    got = np.concatenate([got1, got2, got3])
+    assert (got[:60, 1:] == ref[:60, 1:]).all()
+    assert (got[60:] == ref[60:]).all()
+    assert (S == Sref).all()
