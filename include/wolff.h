@@ -213,7 +213,8 @@ int wolff_batch_set_stream(wolff_batch *b, void *hip_stream);
 
 /* Workgroup size / LDS queue of the batched kernel, picked by the tuner:
  * wg in {64, 128, 256, 512, 1024}, queue entries a power of two in
- * [wg, 8192]. */
+ * [wg, 8192] (queue and claim table, 8 entries per thread, 4 bytes each,
+ * within 64 KiB of LDS); WOLFF_EINVAL otherwise. */
 int wolff_batch_set_tiles(wolff_batch *b, int wg, int queue_entries);
 
 /* Elapsed milliseconds of the last wolff_batch_run's kernel (HIP events on

@@ -259,6 +259,18 @@ __device__ __forceinline__ int8_t expanded_byte(int s0, uint32_t key)
     return (int8_t)(key | 4u | (s0 > 0 ? 2u : 0u));
 }
 
+// ------------------------------------------------------- global pointers
+// A pointer read from memory (a lattice descriptor field) is generic to the
+// compiler, and a generic access is a FLAT instruction, which counts against
+// both the vector-memory and the LDS wait counters: every LDS wait after it
+// would also wait for the global access.  Accesses through these typed
+// pointers are global instructions and leave the LDS counter alone.
+typedef __attribute__((address_space(1))) int8_t gbyte;
+typedef __attribute__((address_space(1))) uint32_t gword;
+
+__device__ __forceinline__ gbyte* as_global(int8_t* p) { return (gbyte*)p; }
+__device__ __forceinline__ gword* as_global(uint32_t* p) { return (gword*)p; }
+
 // ------------------------------------------------------------ wave helpers
 __device__ __forceinline__ uint32_t lane_prefix(uint64_t mask)
 {

@@ -126,7 +126,7 @@ __device__ __forceinline__ void table_claims(uint32_t* tab, const uint32_t a[2 *
 // expanded are counted in n_inner (see run_rep).
 template <int DIM, int WG>
 __device__ __forceinline__ void expand_site_wg(bool active, uint32_t j, const uint32_t nb[2 * DIM],
-                                               const uint32_t sa[2 * DIM], int8_t* S, int s0,
+                                               const uint32_t sa[2 * DIM], gbyte* S, int s0,
                                                uint32_t key, uint32_t thr, uint32_t k0,
                                                uint32_t k1, uint32_t t, uint32_t s,
                                                bool won[2 * DIM], uint32_t* tab,
@@ -482,7 +482,8 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
     const uint32_t wv = tid / WAVE;
 
     int8_t* S = R->S;
-    uint32_t* ov = R->ov;
+    gbyte* SG = as_global(S);
+    gword* ov = as_global(R->ov);
     const Geo g = R->geo;
     const uint32_t thr = R->thr, k0 = R->k0, k1 = R->k1;
     const uint32_t t0 = R->t;
@@ -520,8 +521,8 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
         const uint32_t s = seed_site(k0, k1, t, g.N);             // step (i)
         if (tid == 0) {
             const uint32_t a = site_addr<DIM>(g, s);
-            const int s0 = (S[a] & 2) ? -1 : 1;
-            S[a] = claimed_byte(s0, key);
+            const int s0 = (SG[a] & 2) ? -1 : 1;
+            SG[a] = claimed_byte(s0, key);
             q[0] = s;
             ctl->s0 = s0;
         }
@@ -555,19 +556,19 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
                 // parity: the even one is marked expanded before the step's
                 // reads, the odd one after them.
                 self = site_addr_parity<DIM>(g, j, par);
-                if (active && par == 0u) S[self] = xb;
+                if (active && par == 0u) SG[self] = xb;
                 __syncthreads();
             }
             uint32_t nb[2 * DIM], sa[2 * DIM];
             neighbours<DIM>(g, j, nb, sa);
             bool won[2 * DIM];
-            expand_site_wg<DIM, WG>(active, j, nb, sa, S, s0, key, thr, k0, k1, t, s, won, tab,
+            expand_site_wg<DIM, WG>(active, j, nb, sa, SG, s0, key, thr, k0, k1, t, s, won, tab,
                                     n_anti, n_inner);
             uint32_t pos[2 * DIM];
             const uint32_t wtot = wave_compact<DIM>(won, pos);
             if (lane == 0) wave_cnt[wv] = wtot;
             __syncthreads();
-            if (incr && active && par != 0u) S[self] = xb;           // every read of the step is done
+            if (incr && active && par != 0u) SG[self] = xb;           // every read of the step is done
             // the step's claims are settled: empty the table for the next step
             for (uint32_t i = tid; i < tab_entries(WG); i += WG) tab[i] = TAB_EMPTY;
             uint32_t before = 0u, total = 0u;

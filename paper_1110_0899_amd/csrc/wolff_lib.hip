@@ -231,11 +231,13 @@ static int batch_occupancy(int wg, int dims, int qentries)
     return per_cu * device_cus();
 }
 
+// Workgroup sizes 64..1024 (powers of two); ring entries a power of two in
+// [wg, 8192]; the ring and the claim table within 64 KiB of LDS.
 static bool valid_tiles(int wg, int q)
 {
     if (wg != 64 && wg != 128 && wg != 256 && wg != 512 && wg != 1024) return false;
     if (q < wg || q > 8192 || (q & (q - 1)) != 0) return false;
-    return true;
+    return batch_lds_bytes(wg, (uint32_t)q) <= 65536;
 }
 
 // ====================================================================== sim

@@ -325,3 +325,34 @@ def test_auto_path_follows_cluster_size():
     assert (got[:60, 1:] == ref[:60, 1:]).all()
     assert (got[60:] == ref[60:]).all()
     assert (S == Sref).all()
+
+
+@pytest.mark.parametrize("wg,q", [(64, 64), (128, 128), (256, 2048), (512, 4096), (1024, 1024),
+                                  (1024, 8192)])
+def test_tile_sizes_single_and_batch(wg, q):
+    # every workgroup size / ring size gives the oracle's records; the small
+    # rings overflow to the global stack on the larger lattice
+    cases = [(2, 48, TC2, 7, 80), (3, 12, T3, 8, 60)]
+    for dim, L, T, seed, n in cases:
+        print("case tiles wg=%d q=%d dim=%d L=%d" % (wg, q, dim, L), flush=True)
+        ref, Sref = oracle_series(dim, L, T, seed, n)
+        with binding.Simulation(dim, L, 1.0, T, seed) as sim:
+            sim.set_path(binding.PATH_SINGLE)
+            sim.set_tiles(wg, q)
+            sim.run(n)
+            assert (as_array(sim.observables()) == ref).all()
+            assert (sim.spins() == Sref).all()
+    jobs = [workloads.Job(d, L, T, seed, n) for d, L, T, seed, n in cases]
+    with binding.Batch(jobs) as b:
+        b.set_tiles(wg, q)
+        b.run()
+        for i, (d, L, T, seed, n) in enumerate(cases):
+            ref, _ = oracle_series(d, L, T, seed, n)
+            assert (as_array(b.records(i)) == ref).all()
+
+
+def test_tile_sizes_rejected():
+    with binding.Simulation(2, 16, 1.0, TC2, 1) as sim:
+        for wg, q in [(1024, 16384), (100, 256), (256, 128), (256, 3000), (2048, 4096)]:
+            with pytest.raises(binding.WolffError):
+                sim.set_tiles(wg, q)
