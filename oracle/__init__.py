@@ -15,6 +15,8 @@ builds it with gcc and exposes it through ctypes with numpy arrays:
 * ``cluster(...)``              one cluster, steps (i)-(iv), membership mask
 * ``run(...)``                  n updates, records (B, M, |C|) per update (steps (i)-(v))
 * ``bond_draw(...)``            raw bond random number, for independent graph rebuilds
+* ``potts_*``                   the q-state Potts extension (Section 6): threshold
+                                1 - exp(-J/T), colours, new-colour draw, observables, run
 
 ``Oracle(path)`` wraps any build of the C file (the tests also build
 deliberately broken copies to show that the pins catch them).
@@ -78,6 +80,18 @@ class Oracle:
         lib.orc_run.restype = i32
         lib.orc_bond_draw.argtypes = [u64, u32, u32, u32, i32]
         lib.orc_bond_draw.restype = u32
+        self.has_potts = hasattr(lib, "orc_potts_run")
+        if self.has_potts:
+            lib.orc_potts_threshold.argtypes = [ctypes.c_double, ctypes.c_double]
+            lib.orc_potts_threshold.restype = u32
+            lib.orc_potts_init.argtypes = [i32, i32, i32, u64, p]
+            lib.orc_potts_init.restype = None
+            lib.orc_potts_new_colour.argtypes = [u64, u32, i32, i32]
+            lib.orc_potts_new_colour.restype = i32
+            lib.orc_potts_observables.argtypes = [i32, i32, i32, p, p, p]
+            lib.orc_potts_observables.restype = None
+            lib.orc_potts_run.argtypes = [i32, i32, i32, u32, u64, u32, u64, p, p]
+            lib.orc_potts_run.restype = i32
         self.lib = lib
         self.path = path
 
@@ -135,6 +149,39 @@ class Oracle:
     def bond_draw(self, seed: int, t: int, s: int, b: int, mu: int) -> int:
         return int(self.lib.orc_bond_draw(seed, t, s, b, mu))
 
+    # ---- q-state Potts (Section 6's extension; readings in wolff_oracle.c)
+    def potts_threshold(self, J: float, T: float) -> int:
+        return int(self.lib.orc_potts_threshold(float(J), float(T)))
+
+    def potts_init(self, dim: int, L: int, q: int, seed: int) -> np.ndarray:
+        S = np.zeros(L ** dim, dtype=np.int8)
+        self.lib.orc_potts_init(dim, L, q, seed, _ptr(S))
+        return S
+
+    def potts_new_colour(self, seed: int, t: int, q: int, s0: int) -> int:
+        return int(self.lib.orc_potts_new_colour(seed, t, q, s0))
+
+    def potts_observables(self, dim: int, L: int, q: int, S: np.ndarray) -> tuple[int, int]:
+        S = np.ascontiguousarray(S, dtype=np.int8)
+        B = ctypes.c_int64()
+        M = ctypes.c_int64()
+        self.lib.orc_potts_observables(dim, L, q, _ptr(S), ctypes.addressof(B), ctypes.addressof(M))
+        return B.value, M.value
+
+    def potts_run(self, dim: int, L: int, q: int, thr: int, seed: int, t0: int, n: int,
+                  S: np.ndarray) -> np.ndarray:
+        """Potts updates t0..t0+n-1 on the colours S in place; int64[n, 3] = (B, M, |C|)."""
+        assert S.dtype == np.int8 and S.flags["C_CONTIGUOUS"]
+        rec = np.zeros((max(n, 0), 3), dtype=np.int64)
+        if n == 0:
+            return rec
+        rc = self.lib.orc_potts_run(dim, L, q, thr, seed, t0, n, _ptr(S), _ptr(rec))
+        if rc == -1:
+            raise MemoryError("oracle allocation failed")
+        if rc != 0:
+            raise RuntimeError("oracle consistency check failed (rc=%d)" % rc)
+        return rec
+
 
 def default() -> Oracle:
     global _default
@@ -174,3 +221,23 @@ def run(dim, L, thr, seed, t0, n, S):
 
 def bond_draw(seed, t, s, b, mu):
     return default().bond_draw(seed, t, s, b, mu)
+
+
+def potts_threshold(J, T):
+    return default().potts_threshold(J, T)
+
+
+def potts_init(dim, L, q, seed):
+    return default().potts_init(dim, L, q, seed)
+
+
+def potts_new_colour(seed, t, q, s0):
+    return default().potts_new_colour(seed, t, q, s0)
+
+
+def potts_observables(dim, L, q, S):
+    return default().potts_observables(dim, L, q, S)
+
+
+def potts_run(dim, L, q, thr, seed, t0, n, S):
+    return default().potts_run(dim, L, q, thr, seed, t0, n, S)

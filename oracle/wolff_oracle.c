@@ -84,14 +84,20 @@ static void make_key(uint64_t seed, uint32_t key[2])
 
 /* ------------------------------------------------------------ parameters */
 
-/* thr = floor(p * 2^32), p = 1 - exp(-2J/T) (Section 2, step (ii)). */
-uint32_t orc_threshold(double J, double T)
+/* floor(p * 2^32) in binary64, clamped to [0, 2^32 - 1]. */
+static uint32_t scaled_threshold(double p)
 {
-    const double p = 1.0 - exp(-2.0 * J / T);
     const double scaled = ldexp(p, 32);
     if (!(scaled > 0.0)) return 0u;
     if (scaled >= 4294967295.0) return 0xFFFFFFFFu;
     return (uint32_t)floor(scaled);
+}
+
+/* thr = floor(p * 2^32), p = 1 - exp(-2J/T) (Section 2, step (ii)). */
+uint32_t orc_threshold(double J, double T)
+{
+    const double p = 1.0 - exp(-2.0 * J / T);
+    return scaled_threshold(p);
 }
 
 /* Step (i): the seed site of update t, uniform on [0, N). */
@@ -253,4 +259,93 @@ uint32_t orc_bond_draw(uint64_t seed, uint32_t t, uint32_t s, uint32_t b, int mu
     make_key(seed, key);
     orc_philox4x32_10(ctr, key, r);
     return r[mu];
+}
+
+/* ================================================================ Potts
+ * The q-state Potts model, H = -J sum_<ij> delta(s_i, s_j) with colours
+ * s in {0 .. q-1}, on the same lattices.  Section 6 states that the method
+ * extends to it directly; the readings taken here:
+ *   - bond probability p = 1 - exp(-J / T) between equal colours, the same
+ *     bond keying and threshold compare as the Ising update;
+ *   - the cluster takes one new colour, uniform over the q-1 others:
+ *     new = (s0 + 1 + floor(x0 (q-1) / 2^32)) mod q, x = philox((0, t, 0, 3));
+ *   - initial colour of site i: floor(x0 q / 2^32), x = philox((i, 0, 0, 2));
+ *   - records: B = sum_i sum_mu (q delta(s_i, s_{i+e_mu}) - 1) and
+ *     M = sum_i (q delta(s_i, 0) - 1), so that E = -J (B + d N) / q.
+ * With q = 2 and J_Potts = 2 J_Ising these are the Ising update, spins and
+ * records exactly (colour 0 = +1, colour 1 = -1), which is one of the pins.
+ * The cluster itself is grown by orc_cluster: equal colours, active bonds. */
+
+uint32_t orc_potts_threshold(double J, double T)
+{
+    const double p = 1.0 - exp(-J / T);
+    return scaled_threshold(p);
+}
+
+void orc_potts_init(int dim, int L, int q, uint64_t seed, int8_t *S)
+{
+    const uint64_t N = lattice_sites(dim, L);
+    uint32_t key[2];
+    make_key(seed, key);
+    for (uint64_t i = 0; i < N; ++i) {
+        uint32_t ctr[4] = {(uint32_t)i, 0u, 0u, 2u}, x[4];
+        orc_philox4x32_10(ctr, key, x);
+        S[i] = (int8_t)(((uint64_t)x[0] * (uint64_t)q) >> 32);
+    }
+}
+
+/* The colour that the cluster of update t (seed colour s0) takes. */
+int orc_potts_new_colour(uint64_t seed, uint32_t t, int q, int s0)
+{
+    uint32_t key[2], ctr[4] = {0u, t, 0u, 3u}, x[4];
+    make_key(seed, key);
+    orc_philox4x32_10(ctr, key, x);
+    const int r = (int)(((uint64_t)x[0] * (uint64_t)(q - 1)) >> 32);
+    return (s0 + 1 + r) % q;
+}
+
+void orc_potts_observables(int dim, int L, int q, const int8_t *S, int64_t *B, int64_t *M)
+{
+    const uint64_t N = lattice_sites(dim, L);
+    int64_t b = 0, m = 0;
+    for (uint64_t i = 0; i < N; ++i) {
+        m += (S[i] == 0) ? q - 1 : -1;
+        for (int axis = 0; axis < dim; ++axis) {
+            const uint64_t k = neighbour(dim, L, i, axis, +1);
+            b += (S[i] == S[k]) ? q - 1 : -1;
+        }
+    }
+    *B = b;
+    *M = m;
+}
+
+/* n Potts updates t0 .. t0+n-1 on S in place; rec as orc_run.  Returns 0,
+ * -1 on allocation failure, -2 if M_after = M_before + q |C| (delta(new, 0)
+ * - delta(s0, 0)) fails. */
+int orc_potts_run(int dim, int L, int q, uint32_t thr, uint64_t seed, uint32_t t0, uint64_t n,
+                  int8_t *S, int64_t *rec)
+{
+    const uint64_t N = lattice_sites(dim, L);
+    uint8_t *member = (uint8_t *)malloc((size_t)N);
+    if (!member) return -1;
+    int64_t B, M;
+    orc_potts_observables(dim, L, q, S, &B, &M);
+    for (uint64_t u = 0; u < n; ++u) {
+        const uint32_t t = t0 + (uint32_t)u;
+        uint64_t s;
+        int s0;
+        const uint64_t csize = orc_cluster(dim, L, thr, seed, t, S, member, &s, &s0);
+        if (csize == 0) { free(member); return -1; }
+        const int c = orc_potts_new_colour(seed, t, q, s0);
+        for (uint64_t i = 0; i < N; ++i) S[i] = member[i] ? (int8_t)c : S[i];
+        const int64_t M_prev = M;
+        orc_potts_observables(dim, L, q, S, &B, &M);
+        const int64_t dz = (int64_t)(c == 0) - (int64_t)(s0 == 0);
+        if (M != M_prev + (int64_t)q * (int64_t)csize * dz) { free(member); return -2; }
+        rec[3 * u + 0] = B;
+        rec[3 * u + 1] = M;
+        rec[3 * u + 2] = (int64_t)csize;
+    }
+    free(member);
+    return 0;
 }
