@@ -274,11 +274,13 @@ def sizes_leg(binding, workloads, cpu_seconds):
     """The paper's size sweep (Tables 1-2) at T_c."""
     rows = []
     for dim, Ls, T, warm, steps in ((2, (512, 1024, 2048, 4096), workloads.TC_2D, 300, 300),
-                                    (3, (64, 128, 256), workloads.T_3D, 1000, 1000)):
+                                    (3, (64, 128, 256, 1024), workloads.T_3D, 1000, 1000)):
         for L in Ls:
+            # 3D L=1024 (1 GiB of spins) is the size the paper expected to gain most
             r = sweep_point(binding, dim, L, T, 2 if dim == 2 else 3, warm, steps, True, cpu_seconds)
-            r["paper_ms"] = dict(zip(("gpu_update_only", "gpu_measure", "cpu_update_only",
-                                      "cpu_measure"), PAPER_TABLES[(dim, L)]))
+            if (dim, L) in PAPER_TABLES:
+                r["paper_ms"] = dict(zip(("gpu_update_only", "gpu_measure", "cpu_update_only",
+                                          "cpu_measure"), PAPER_TABLES[(dim, L)]))
             rows.append(r)
     return rows
 

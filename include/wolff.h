@@ -69,12 +69,15 @@ typedef struct {
     double   J;
     double   T;
     uint64_t seed;
-    uint32_t threshold;      /* thr = floor((1 - exp(-2J/T)) * 2^32)           */
+    uint32_t threshold;      /* thr = floor((1 - exp(-2J/T)) * 2^32); Potts:
+                                floor((1 - exp(-J/T)) * 2^32)                 */
     int32_t  path;           /* WOLFF_PATH_* the next wolff_run will use       */
     uint64_t t;              /* index of the next update                       */
     int64_t  mag;            /* magnetisation after the last update            */
     int64_t  bond_sum;       /* bond sum after the last measured update        */
     uint64_t records_pending;/* records not yet drained by wolff_observables   */
+    int32_t  q;              /* 0: Ising; q >= 2: q-state Potts (wolff_create_potts) */
+    int32_t  reserved;
 } wolff_info;
 
 typedef struct wolff_sim wolff_sim;
@@ -86,6 +89,22 @@ typedef struct wolff_sim wolff_sim;
  * multi-workgroup queue on the first team-path run.
  * Synchronises before returning.  *out is set only on success. */
 int wolff_create(int dim, int L, double J, double T, uint64_t seed, wolff_sim **out);
+
+/* The q-state Potts model, H = -J sum_<ij> delta(s_i, s_j), colours
+ * 0 .. q-1 (the extension Section 6 calls straightforward), 2 <= q <= 127:
+ * bonds between equal colours are active with p = 1 - exp(-J/T) (the Ising
+ * bond keying and threshold compare), and each cluster takes a new colour
+ * uniform over the q - 1 others, drawn from word 0 of philox((0, t, 0, 3)).
+ * Initial colours floor(x0 q / 2^32), x = philox((i, 0, 0, 2)).  Records:
+ * bond_sum = sum over bonds of (q delta - 1), so E = -J (bond_sum + d N) / q;
+ * mag = q (number of colour-0 sites) - N.  Spins are colours (int8) in
+ * wolff_get_spins / wolff_set_spins.  With q = 2 and J twice the Ising J
+ * the update, spins (colour 0 = +1) and records are the Ising ones.
+ * Potts lattices run on the one-workgroup path (WOLFF_PATH_TEAM is
+ * WOLFF_EINVAL) with a lattice recount per measured update.  Otherwise as
+ * wolff_create. */
+int wolff_create_potts(int dim, int L, int q, double J, double T, uint64_t seed,
+                       wolff_sim **out);
 
 /* Release the handle and its device memory (waits for its stream). NULL is ok. */
 int wolff_destroy(wolff_sim *s);
@@ -176,10 +195,14 @@ typedef struct {
     uint64_t seed;
     uint64_t n_updates;      /* updates this replica still has to run        */
     int32_t  start;          /* initial spins: 0 iid +-1 from seed (as in
-                                wolff_create), +1 all up, -1 all down         */
+                                wolff_create), +1 all up, -1 all down; Potts:
+                                iid colours, all colour 0, all colour 1       */
     int32_t  flags;          /* 0, or WOLFF_JOB_UPDATE_ONLY: records carry
                                 bond_sum = WOLFF_NOT_MEASURED (the paper's
                                 "update only"); mag and csize stay exact      */
+    int32_t  q;              /* 0: Ising; 2..127: q-state Potts (as
+                                wolff_create_potts)                            */
+    int32_t  reserved;       /* 0                                              */
 } wolff_job;
 
 #define WOLFF_JOB_UPDATE_ONLY 1

@@ -40,13 +40,15 @@ class Info(ctypes.Structure):
                 ("J", ctypes.c_double), ("T", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("threshold", ctypes.c_uint32), ("path", ctypes.c_int32), ("t", ctypes.c_uint64),
                 ("mag", ctypes.c_int64), ("bond_sum", ctypes.c_int64),
-                ("records_pending", ctypes.c_uint64)]
+                ("records_pending", ctypes.c_uint64), ("q", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class JobDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("L", ctypes.c_int32), ("J", ctypes.c_double),
                 ("T", ctypes.c_double), ("seed", ctypes.c_uint64), ("n_updates", ctypes.c_uint64),
-                ("start", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("start", ctypes.c_int32), ("flags", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 JOB_UPDATE_ONLY = 1
@@ -71,6 +73,7 @@ _I = ctypes.c_int
 _D = ctypes.c_double
 SIGNATURES = {
     "wolff_create": (_I, [_I, _I, _D, _D, _U64, ctypes.POINTER(_P)]),
+    "wolff_create_potts": (_I, [_I, _I, _I, _D, _D, _U64, ctypes.POINTER(_P)]),
     "wolff_destroy": (_I, [_P]),
     "wolff_run": (_I, [_P, _U64]),
     "wolff_observables": (_I, [_P, _P, _U64, ctypes.POINTER(_U64)]),
@@ -146,15 +149,20 @@ def _stream_handle(stream) -> int | None:
 
 
 class Simulation:
-    """One lattice: wolff_create / wolff_run / wolff_observables."""
+    """One lattice: wolff_create / wolff_run / wolff_observables; with q >= 2
+    the q-state Potts model (wolff_create_potts)."""
 
-    def __init__(self, dim: int, L: int, J: float, T: float, seed: int):
+    def __init__(self, dim: int, L: int, J: float, T: float, seed: int, q: int = 0):
         lib = load()
         h = ctypes.c_void_p()
-        _check(lib.wolff_create(dim, L, float(J), float(T), int(seed), ctypes.byref(h)),
-               "wolff_create")
+        if q:
+            _check(lib.wolff_create_potts(dim, L, int(q), float(J), float(T), int(seed),
+                                          ctypes.byref(h)), "wolff_create_potts")
+        else:
+            _check(lib.wolff_create(dim, L, float(J), float(T), int(seed), ctypes.byref(h)),
+                   "wolff_create")
         self._h = h
-        self.dim, self.L, self.J, self.T, self.seed = dim, L, J, T, seed
+        self.dim, self.L, self.J, self.T, self.seed, self.q = dim, L, J, T, seed, q
         self.n_sites = L ** dim
 
     def close(self):
@@ -235,14 +243,15 @@ class Batch:
     """Many replicas advanced by one persistent launch per run()."""
 
     def __init__(self, jobs, start: int = 0, update_only: bool = False):
-        """jobs: objects with dim, L, J, T, seed, n_updates; start: 0 iid +-1
-        from each seed, +1 / -1 ordered; update_only: no bond sum per update."""
+        """jobs: objects with dim, L, J, T, seed, n_updates (and q: 0 Ising,
+        >= 2 Potts); start: 0 iid +-1 (colours) from each seed, +1 / -1
+        ordered; update_only: no bond sum per update."""
         lib = load()
         arr = (JobDesc * len(jobs))()
         flags = JOB_UPDATE_ONLY if update_only else 0
         for i, j in enumerate(jobs):
             arr[i] = JobDesc(j.dim, j.L, float(j.J), float(j.T), int(j.seed), int(j.n_updates),
-                             int(start), flags)
+                             int(start), flags, int(getattr(j, "q", 0)), 0)
         h = ctypes.c_void_p()
         _check(lib.wolff_batch_create(arr, len(jobs), ctypes.byref(h)), "wolff_batch_create")
         self._h = h
@@ -338,7 +347,7 @@ class Server:
 
     def submit(self, job, start: int = 0, update_only: bool = False) -> int:
         d = JobDesc(job.dim, job.L, float(job.J), float(job.T), int(job.seed), int(job.n_updates),
-                    int(start), JOB_UPDATE_ONLY if update_only else 0)
+                    int(start), JOB_UPDATE_ONLY if update_only else 0, int(getattr(job, "q", 0)), 0)
         jid = _U64()
         _check(load().wolff_server_submit(self._h, ctypes.byref(d), ctypes.byref(jid)),
                "wolff_server_submit")

@@ -41,6 +41,7 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 constexpr uint32_t DOMAIN_BOND = 0u;
 constexpr uint32_t DOMAIN_SEED = 1u;
 constexpr uint32_t DOMAIN_INIT = 2u;
+constexpr uint32_t DOMAIN_COLOUR = 3u;   // q-state Potts: the cluster's new colour
 
 // Seed site of update t: the 64-bit draw (x1:x0) scaled onto [0, N) by a
 // multiply-high, exactly uniform for N a power of two.
@@ -49,6 +50,17 @@ __device__ __forceinline__ uint32_t seed_site(uint32_t k0, uint32_t k1, uint32_t
     const U4 x = philox(0u, t, 0u, DOMAIN_SEED, k0, k1);
     const uint64_t u = ((uint64_t)x.y << 32) | x.x;
     return (uint32_t)__umul64hi(u, (uint64_t)N);
+}
+
+// q-state Potts (q >= 2): the colour that the cluster of update t, seed
+// colour s0, takes: uniform over the q - 1 others,
+// s0 + 1 + floor(x0 (q - 1) / 2^32) mod q with x = philox((0, t, 0, 3)).
+__device__ __forceinline__ uint32_t potts_new_colour(uint32_t k0, uint32_t k1, uint32_t t,
+                                                     uint32_t q, uint32_t s0)
+{
+    const U4 x = philox(0u, t, 0u, DOMAIN_COLOUR, k0, k1);
+    const uint32_t c = s0 + 1u + __umulhi(x.x, q - 1u);
+    return c >= q ? c - q : c;
 }
 
 // ---------------------------------------------------------------- geometry

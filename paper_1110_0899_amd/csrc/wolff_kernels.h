@@ -35,6 +35,8 @@ struct Rep {
     uint32_t err;           // error bits (ERR_*)
     uint32_t t_norm;        // no member tag in S is older than update t_norm
     uint32_t b_valid;       // 1: B holds the bond sum of the current lattice
+    uint32_t q;             // 0: Ising (+-1 bytes); q >= 2: q-state Potts (colour bytes)
+    uint32_t pad_q;
     int64_t M;              // magnetisation after the last update
     int64_t B;              // bond sum (valid when b_valid)
 };

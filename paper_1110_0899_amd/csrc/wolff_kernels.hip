@@ -120,19 +120,22 @@ __device__ __forceinline__ void table_claims(uint32_t* tab, const uint32_t a[2 *
 }
 
 // One-workgroup path.  `key` is the tag of the update (NO_TAG: plain bytes).
-// Members of the cluster hold -s0, so a neighbour is eligible exactly when
-// its sign is s0.  A neighbour of sign -s0 is a member (original spin s0)
-// or an anti-aligned non-member, counted in n_anti; members already
-// expanded are counted in n_inner (see run_rep).
+// Ising: members of the cluster hold -s0, so a neighbour is eligible exactly
+// when its sign is s0.  A neighbour of sign -s0 is a member (original spin
+// s0) or an anti-aligned non-member, counted in n_anti; members already
+// expanded are counted in n_inner (see run_rep).  Potts: members hold the
+// new colour, so a neighbour is eligible exactly when its colour is s0.
+// A neighbour byte b is eligible when (b & emask) == evalue: the sign bit
+// for Ising, the whole colour byte for Potts.  A claimed site gets byte cb.
 template <int DIM, int WG>
 __device__ __forceinline__ void expand_site_wg(bool active, uint32_t j, const uint32_t nb[2 * DIM],
-                                               const uint32_t sa[2 * DIM], gbyte* S, int s0,
+                                               const uint32_t sa[2 * DIM], gbyte* S,
+                                               uint32_t emask, uint32_t evalue, int8_t cb,
                                                uint32_t key, uint32_t thr, uint32_t k0,
                                                uint32_t k1, uint32_t t, uint32_t s,
                                                bool won[2 * DIM], uint32_t* tab,
                                                uint32_t& n_anti, uint32_t& n_inner)
 {
-    const uint32_t neg0 = s0 < 0 ? 2u : 0u;            // bit 1 of an s0 byte
     uint32_t b[2 * DIM];
 #pragma unroll
     for (int m = 0; m < 2 * DIM; ++m) b[m] = (uint8_t)S[sa[m]];
@@ -141,14 +144,13 @@ __device__ __forceinline__ void expand_site_wg(bool active, uint32_t j, const ui
     bool act[2 * DIM];
 #pragma unroll
     for (int m = 0; m < 2 * DIM; ++m) {
-        const bool same = (b[m] & 2u) == neg0;
+        const bool same = (b[m] & emask) == evalue;
         const uint32_t r = (m & 1) ? rm[m / 2] : rp[m / 2];
         act[m] = active && same && r < thr;
         n_anti += (active && !same && !is_member(b[m], key)) ? 1u : 0u;
         n_inner += (active && is_expanded(b[m], key)) ? 1u : 0u;
     }
     table_claims<WG, DIM>(tab, sa, act, won);
-    const int8_t cb = claimed_byte(s0, key);
 #pragma unroll
     for (int m = 0; m < 2 * DIM; ++m)
         if (won[m]) S[sa[m]] = cb;
@@ -182,7 +184,41 @@ __device__ __forceinline__ uint32_t wave_compact(const bool won[2 * DIM], uint32
 // The +x neighbours are the chunk shifted by one byte plus the first byte of
 // the next chunk of the row (wrapping to the row start); +y / +z are the
 // chunks one row / one plane further (periodic).
-template <int DIM>
+// Per-word counts of 4 spin bytes.  Ising (+1 = 0x01, -1 = 0xFF, tags keep
+// the sign in bit 1): pair_count = bonds whose spins differ, self_count =
+// spins equal to -1.  Potts (colour bytes): pair_count = bonds whose colours
+// are equal, self_count = sites of colour 0; a zero byte of v is detected
+// exactly by the high bit of ~(((v & 0x7F..) + 0x7F..) | v | 0x7F..).
+__device__ __forceinline__ uint32_t zero_bytes(uint32_t v)
+{
+    return __popc(~(((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v | 0x7F7F7F7Fu));
+}
+
+template <bool POTTS>
+__device__ __forceinline__ uint32_t pair_count(uint32_t a, uint32_t b)
+{
+    return POTTS ? zero_bytes(a ^ b) : __popc((a ^ b) & 0x02020202u);
+}
+
+template <bool POTTS>
+__device__ __forceinline__ uint32_t self_count(uint32_t a)
+{
+    return POTTS ? zero_bytes(a) : __popc(a & 0x02020202u);
+}
+
+template <bool POTTS>
+__device__ __forceinline__ uint32_t pair_count1(uint32_t a, uint32_t b)
+{
+    return POTTS ? (uint32_t)(a == b) : ((a ^ b) >> 1) & 1u;
+}
+
+template <bool POTTS>
+__device__ __forceinline__ uint32_t self_count1(uint32_t a)
+{
+    return POTTS ? (uint32_t)(a == 0u) : (a >> 1) & 1u;
+}
+
+template <int DIM, bool POTTS>
 __device__ __forceinline__ void chunk_counts(const int8_t* S, const Geo& g, uint32_t c,
                                              uint32_t& ndiff, uint32_t& nneg)
 {
@@ -195,13 +231,12 @@ __device__ __forceinline__ void chunk_counts(const int8_t* S, const Geo& g, uint
     const uint4 a = S4[c];
     const uint32_t inext = (x0 + 16u == L) ? i + 16u - L : i + 16u;
     const uint32_t w4 = S1[inext >> 2];
-    const uint32_t K = 0x02020202u;
     const uint32_t s0 = (a.x >> 8) | (a.y << 24);
     const uint32_t s1 = (a.y >> 8) | (a.z << 24);
     const uint32_t s2 = (a.z >> 8) | (a.w << 24);
     const uint32_t s3 = (a.w >> 8) | (w4 << 24);
-    uint32_t d = __popc((a.x ^ s0) & K) + __popc((a.y ^ s1) & K) + __popc((a.z ^ s2) & K) +
-                 __popc((a.w ^ s3) & K);
+    uint32_t d = pair_count<POTTS>(a.x, s0) + pair_count<POTTS>(a.y, s1) + pair_count<POTTS>(a.z, s2) +
+                 pair_count<POTTS>(a.w, s3);
     uint32_t iy;
     if (DIM == 2) {
         iy = (i >= N - L) ? i - (N - L) : i + L;
@@ -210,23 +245,23 @@ __device__ __forceinline__ void chunk_counts(const int8_t* S, const Geo& g, uint
         iy = (y + 1u == L) ? i + L - LL : i + L;
     }
     const uint4 b = S4[iy >> 4];
-    d += __popc((a.x ^ b.x) & K) + __popc((a.y ^ b.y) & K) + __popc((a.z ^ b.z) & K) +
-         __popc((a.w ^ b.w) & K);
+    d += pair_count<POTTS>(a.x, b.x) + pair_count<POTTS>(a.y, b.y) + pair_count<POTTS>(a.z, b.z) +
+         pair_count<POTTS>(a.w, b.w);
     if (DIM == 3) {
         const uint32_t iz = (i >= N - LL) ? i - (N - LL) : i + LL;
         const uint4 z = S4[iz >> 4];
-        d += __popc((a.x ^ z.x) & K) + __popc((a.y ^ z.y) & K) + __popc((a.z ^ z.z) & K) +
-             __popc((a.w ^ z.w) & K);
+        d += pair_count<POTTS>(a.x, z.x) + pair_count<POTTS>(a.y, z.y) + pair_count<POTTS>(a.z, z.z) +
+             pair_count<POTTS>(a.w, z.w);
     }
     ndiff = d;
-    nneg = __popc(a.x & K) + __popc(a.y & K) + __popc(a.z & K) + __popc(a.w & K);
+    nneg = self_count<POTTS>(a.x) + self_count<POTTS>(a.y) + self_count<POTTS>(a.z) + self_count<POTTS>(a.w);
 }
 
 // Tiled storage: chunk c is row (c & 7) of tile c >> 3, 16 sites along x.
 // The +x neighbours are the row shifted by one byte plus the first byte of
 // the same row of the next tile along x; +y / +z neighbours are the next row
 // of the tile or the matching row of the next tile (periodic).
-template <int DIM>
+template <int DIM, bool POTTS>
 __device__ __forceinline__ void chunk_counts_tiled(const int8_t* S, const Geo& g, uint32_t c,
                                                    uint32_t& ndiff, uint32_t& nneg)
 {
@@ -238,13 +273,12 @@ __device__ __forceinline__ void chunk_counts_tiled(const int8_t* S, const Geo& g
     const uint32_t Tx = (tx + 1u == g.ntx) ? T - tx : T + 1u;
     const uint4 a = S4[c];
     const uint32_t w4 = S1[((Tx << 3) | row) << 2];
-    const uint32_t K = 0x02020202u;
     const uint32_t s0 = (a.x >> 8) | (a.y << 24);
     const uint32_t s1 = (a.y >> 8) | (a.z << 24);
     const uint32_t s2 = (a.z >> 8) | (a.w << 24);
     const uint32_t s3 = (a.w >> 8) | (w4 << 24);
-    uint32_t d = __popc((a.x ^ s0) & K) + __popc((a.y ^ s1) & K) + __popc((a.z ^ s2) & K) +
-                 __popc((a.w ^ s3) & K);
+    uint32_t d = pair_count<POTTS>(a.x, s0) + pair_count<POTTS>(a.y, s1) + pair_count<POTTS>(a.z, s2) +
+                 pair_count<POTTS>(a.w, s3);
     uint32_t cy;
     if (DIM == 2) {
         const uint32_t ty = q1;
@@ -274,20 +308,20 @@ __device__ __forceinline__ void chunk_counts_tiled(const int8_t* S, const Geo& g
             cz = (Tz << 3) | oy;
         }
         const uint4 z = S4[cz];
-        d += __popc((a.x ^ z.x) & K) + __popc((a.y ^ z.y) & K) + __popc((a.z ^ z.z) & K) +
-             __popc((a.w ^ z.w) & K);
+        d += pair_count<POTTS>(a.x, z.x) + pair_count<POTTS>(a.y, z.y) + pair_count<POTTS>(a.z, z.z) +
+             pair_count<POTTS>(a.w, z.w);
     }
     const uint4 b = S4[cy];
-    d += __popc((a.x ^ b.x) & K) + __popc((a.y ^ b.y) & K) + __popc((a.z ^ b.z) & K) +
-         __popc((a.w ^ b.w) & K);
+    d += pair_count<POTTS>(a.x, b.x) + pair_count<POTTS>(a.y, b.y) + pair_count<POTTS>(a.z, b.z) +
+         pair_count<POTTS>(a.w, b.w);
     ndiff = d;
-    nneg = __popc(a.x & K) + __popc(a.y & K) + __popc(a.z & K) + __popc(a.w & K);
+    nneg = self_count<POTTS>(a.x) + self_count<POTTS>(a.y) + self_count<POTTS>(a.z) + self_count<POTTS>(a.w);
 }
 
 // Scalar form for any L: per site, with coordinates advanced incrementally
 // along the thread's stride (no division in the loop).  Accumulates the same
 // two counts as the vector form.
-template <int DIM>
+template <int DIM, bool POTTS>
 __device__ __forceinline__ void scalar_counts(const int8_t* S, const Geo& g, uint32_t first,
                                               uint32_t stride, uint32_t& ndiff, uint32_t& nneg)
 {
@@ -299,20 +333,20 @@ __device__ __forceinline__ void scalar_counts(const int8_t* S, const Geo& g, uin
     const uint32_t dx = stride - dq * L;
     const uint32_t dq_mod = dq - g.div_L(dq) * L;
     uint32_t d = 0u, neg = 0u;
-    // only bit 1 (the sign) of a byte is read: bytes may carry member tags
+    // Ising: only bit 1 (the sign) of a byte is read: bytes may carry member tags
     for (uint32_t i = first; i < N; i += stride) {
         const uint32_t si = (uint8_t)S[i];
         const uint32_t xp = (x + 1u == L) ? i + 1u - L : i + 1u;
-        d += (((uint8_t)S[xp] ^ si) >> 1) & 1u;
+        d += pair_count1<POTTS>((uint8_t)S[xp], si);
         if (DIM == 2) {
             const uint32_t yp = (i >= N - L) ? i - (N - L) : i + L;
-            d += (((uint8_t)S[yp] ^ si) >> 1) & 1u;
+            d += pair_count1<POTTS>((uint8_t)S[yp], si);
         } else {
             const uint32_t yp = (y + 1u == L) ? i + L - LL : i + L;
             const uint32_t zp = (i >= N - LL) ? i - (N - LL) : i + LL;
-            d += ((((uint8_t)S[yp] ^ si) >> 1) & 1u) + ((((uint8_t)S[zp] ^ si) >> 1) & 1u);
+            d += pair_count1<POTTS>((uint8_t)S[yp], si) + pair_count1<POTTS>((uint8_t)S[zp], si);
         }
-        neg += (si >> 1) & 1u;
+        neg += self_count1<POTTS>(si);
         x += dx;
         uint32_t carry = 0u;
         if (x >= L) {
@@ -332,7 +366,7 @@ __device__ __forceinline__ void scalar_counts(const int8_t* S, const Geo& g, uin
 // stride, ... (chunks when L % 16 == 0, sites otherwise).  UNROLL chunks are
 // in flight per thread: 4 in the grid-wide kernel, 1 inside the growth
 // kernel, where the registers of four chunks would halve the resident waves.
-template <int DIM, int UNROLL>
+template <int DIM, int UNROLL, bool POTTS = false>
 __device__ __forceinline__ void lattice_counts(const int8_t* S, const Geo& g, uint32_t first,
                                                uint32_t stride, uint64_t& ndiff, uint64_t& nneg)
 {
@@ -343,17 +377,17 @@ __device__ __forceinline__ void lattice_counts(const int8_t* S, const Geo& g, ui
         if (UNROLL == 4) {
             for (; c + 3u * stride < nchunks; c += 4u * stride) {
                 uint32_t d0, n0, d1, n1, d2, n2, d3, n3;
-                chunk_counts_tiled<DIM>(S, g, c, d0, n0);
-                chunk_counts_tiled<DIM>(S, g, c + stride, d1, n1);
-                chunk_counts_tiled<DIM>(S, g, c + 2u * stride, d2, n2);
-                chunk_counts_tiled<DIM>(S, g, c + 3u * stride, d3, n3);
+                chunk_counts_tiled<DIM, POTTS>(S, g, c, d0, n0);
+                chunk_counts_tiled<DIM, POTTS>(S, g, c + stride, d1, n1);
+                chunk_counts_tiled<DIM, POTTS>(S, g, c + 2u * stride, d2, n2);
+                chunk_counts_tiled<DIM, POTTS>(S, g, c + 3u * stride, d3, n3);
                 d += d0 + d1 + d2 + d3;
                 neg += n0 + n1 + n2 + n3;
             }
         }
         for (; c < nchunks; c += stride) {
             uint32_t d0, n0;
-            chunk_counts_tiled<DIM>(S, g, c, d0, n0);
+            chunk_counts_tiled<DIM, POTTS>(S, g, c, d0, n0);
             d += d0;
             neg += n0;
         }
@@ -363,23 +397,23 @@ __device__ __forceinline__ void lattice_counts(const int8_t* S, const Geo& g, ui
         if (UNROLL == 4) {
             for (; c + 3u * stride < nchunks; c += 4u * stride) {
                 uint32_t d0, n0, d1, n1, d2, n2, d3, n3;
-                chunk_counts<DIM>(S, g, c, d0, n0);
-                chunk_counts<DIM>(S, g, c + stride, d1, n1);
-                chunk_counts<DIM>(S, g, c + 2u * stride, d2, n2);
-                chunk_counts<DIM>(S, g, c + 3u * stride, d3, n3);
+                chunk_counts<DIM, POTTS>(S, g, c, d0, n0);
+                chunk_counts<DIM, POTTS>(S, g, c + stride, d1, n1);
+                chunk_counts<DIM, POTTS>(S, g, c + 2u * stride, d2, n2);
+                chunk_counts<DIM, POTTS>(S, g, c + 3u * stride, d3, n3);
                 d += d0 + d1 + d2 + d3;
                 neg += n0 + n1 + n2 + n3;
             }
         }
         for (; c < nchunks; c += stride) {
             uint32_t d0, n0;
-            chunk_counts<DIM>(S, g, c, d0, n0);
+            chunk_counts<DIM, POTTS>(S, g, c, d0, n0);
             d += d0;
             neg += n0;
         }
     } else {
         uint32_t d0 = 0u, n0 = 0u;
-        if (first < g.N) scalar_counts<DIM>(S, g, first, stride, d0, n0);
+        if (first < g.N) scalar_counts<DIM, POTTS>(S, g, first, stride, d0, n0);
         d = d0;
         neg = n0;
     }
@@ -395,14 +429,18 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
 }
 
 // (B, M) of one lattice by one workgroup; every thread receives the result.
+// Potts (q > 0): B = q (equal bonds) - d N, M = q (colour-0 sites) - N.
 template <int WG, int DIM>
 __device__ __forceinline__ void reduce_lattice_wg(const int8_t* S, const Geo& g, long long* red,
-                                  int64_t& Bout, int64_t& Mout)
+                                  int64_t& Bout, int64_t& Mout, uint32_t q = 0u)
 {
     constexpr int NW = WG / WAVE;
     const uint32_t tid = threadIdx.x;
     uint64_t d, neg;
-    lattice_counts<DIM, 1>(S, g, tid, WG, d, neg);
+    if (q)
+        lattice_counts<DIM, 1, true>(S, g, tid, WG, d, neg);
+    else
+        lattice_counts<DIM, 1, false>(S, g, tid, WG, d, neg);
     d = wave_sum_u64(d);
     neg = wave_sum_u64(neg);
     const uint32_t wv = tid / WAVE;
@@ -418,8 +456,13 @@ __device__ __forceinline__ void reduce_lattice_wg(const int8_t* S, const Geo& g,
         sd += red[w];
         sn += red[NW + w];
     }
-    Bout = (int64_t)DIM * (int64_t)g.N - 2 * sd;
-    Mout = (int64_t)g.N - 2 * sn;
+    if (q) {
+        Bout = (int64_t)q * sd - (int64_t)DIM * (int64_t)g.N;
+        Mout = (int64_t)q * sn - (int64_t)g.N;
+    } else {
+        Bout = (int64_t)DIM * (int64_t)g.N - 2 * sd;
+        Mout = (int64_t)g.N - 2 * sn;
+    }
     __syncthreads();
 }
 
@@ -458,10 +501,10 @@ __device__ __forceinline__ void clear_tags_wg(int8_t* S, uint32_t N)
 // over the waves' counts in LDS, one store per new site.
 // Workgroup-shared control words of the one-workgroup path.
 struct WgCtl {
-    int s0;                 // seed spin of the current update
+    int s0;                 // seed spin (Ising) or colour (Potts) of the current update
     uint32_t stop;          // 1: the launch's time budget is spent
     uint32_t idx;           // next replica (work counter)
-    uint32_t pad;
+    int32_t cb;             // byte written to claimed sites
     uint64_t t_start;       // wall clock at the workgroup's start
 };
 
@@ -494,9 +537,10 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
     bool b_valid = R->b_valid != 0u;
     uint32_t t_norm = R->t_norm;
     const bool measure = R->measure != 0u;
-    // With measurement on an even-L (bipartite) lattice the bond sum follows
-    // the cluster; otherwise it is recounted over the lattice per update.
-    const bool incr = measure && (g.L & 1u) == 0u;
+    const uint32_t pq = R->q;                                     // 0: Ising, else Potts q
+    // With measurement on an even-L (bipartite) Ising lattice the bond sum
+    // follows the cluster; otherwise it is recounted over the lattice per update.
+    const bool incr = measure && pq == 0u && (g.L & 1u) == 0u;
     uint32_t err = 0u;
     const uint32_t QC = qmask + 1u;
     uint32_t* tab = q + QC;                                       // claim table after the ring
@@ -521,13 +565,26 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
         const uint32_t s = seed_site(k0, k1, t, g.N);             // step (i)
         if (tid == 0) {
             const uint32_t a = site_addr<DIM>(g, s);
-            const int s0 = (SG[a] & 2) ? -1 : 1;
-            SG[a] = claimed_byte(s0, key);
+            const uint32_t b0 = (uint8_t)SG[a];
+            int s0;
+            int8_t cbyte;
+            if (pq) {
+                s0 = (int)b0;
+                cbyte = (int8_t)potts_new_colour(k0, k1, t, pq, b0);
+            } else {
+                s0 = (b0 & 2u) ? -1 : 1;
+                cbyte = claimed_byte(s0, key);
+            }
+            SG[a] = cbyte;
             q[0] = s;
             ctl->s0 = s0;
+            ctl->cb = cbyte;
         }
         __syncthreads();
         const int s0 = ctl->s0;
+        const int8_t cb = (int8_t)ctl->cb;
+        const uint32_t emask = pq ? 0xFFu : 2u;
+        const uint32_t evalue = pq ? (uint32_t)s0 : (s0 < 0 ? 2u : 0u);
         const int8_t xb = expanded_byte(s0, key);
 
         uint32_t head = 0u, tail = 1u, ovn = 0u;                    // the paper's in / ic
@@ -562,8 +619,8 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
             uint32_t nb[2 * DIM], sa[2 * DIM];
             neighbours<DIM>(g, j, nb, sa);
             bool won[2 * DIM];
-            expand_site_wg<DIM, WG>(active, j, nb, sa, SG, s0, key, thr, k0, k1, t, s, won, tab,
-                                    n_anti, n_inner);
+            expand_site_wg<DIM, WG>(active, j, nb, sa, SG, emask, evalue, cb, key, thr, k0, k1, t,
+                                    s, won, tab, n_anti, n_inner);
             uint32_t pos[2 * DIM];
             const uint32_t wtot = wave_compact<DIM>(won, pos);
             if (lane == 0) wave_cnt[wv] = wtot;
@@ -593,7 +650,10 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
             __syncthreads();
         }
 
-        M -= 2 * (int64_t)s0 * (int64_t)csize;                     // exact |dM| = 2|C|
+        if (pq)                                                     // exact: colour-0 count moves by +-|C|
+            M += (int64_t)pq * (int64_t)csize * ((int64_t)(cb == 0) - (int64_t)(s0 == 0));
+        else
+            M -= 2 * (int64_t)s0 * (int64_t)csize;                  // exact |dM| = 2|C|
         if (incr) {
             // Flipping C changes only the bonds between C and the rest: with
             // n_anti of them anti-aligned and 2d|C| - n_anti - 2 n_inner
@@ -607,7 +667,7 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
             B -= 4 * ((int64_t)DIM * (int64_t)csize - sum);
         } else if (measure) {
             int64_t Bm, Mm;
-            reduce_lattice_wg<WG, DIM>(S, g, red, Bm, Mm);
+            reduce_lattice_wg<WG, DIM>(S, g, red, Bm, Mm, pq);
             B = Bm;
             if (Mm != M) err |= ERR_MAG;
         }
@@ -696,15 +756,18 @@ __global__ void reset_counter_kernel(uint32_t* c)
     if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0u;
 }
 
-// Initial state: iid +-1 from the domain-2 stream (site i named logically,
-// stored at its address).
-__global__ void init_kernel(int8_t* S, Geo g, int dim, uint32_t k0, uint32_t k1)
+// Initial state: iid +-1 (Ising) or iid colours (Potts) from the domain-2
+// stream (site i named logically, stored at its address).
+__global__ void init_kernel(int8_t* S, Geo g, int dim, uint32_t k0, uint32_t k1, uint32_t q)
 {
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += stride) {
         const U4 r = philox(i, 0u, 0u, DOMAIN_INIT, k0, k1);
         const uint32_t a = (dim == 2) ? site_addr<2>(g, i) : site_addr<3>(g, i);
-        S[a] = (r.x < 0x80000000u) ? (int8_t)1 : (int8_t)-1;
+        if (q)                                            // Potts colour floor(x0 q / 2^32)
+            S[a] = (int8_t)__umulhi(r.x, q);
+        else
+            S[a] = (r.x < 0x80000000u) ? (int8_t)1 : (int8_t)-1;
     }
 }
 
@@ -716,9 +779,9 @@ __global__ __launch_bounds__(WG) void measure_rep_kernel(Rep* R)
     int64_t B, M;
     const Geo g = R->geo;
     if (R->dim == 2)
-        reduce_lattice_wg<WG, 2>(R->S, g, red, B, M);
+        reduce_lattice_wg<WG, 2>(R->S, g, red, B, M, R->q);
     else
-        reduce_lattice_wg<WG, 3>(R->S, g, red, B, M);
+        reduce_lattice_wg<WG, 3>(R->S, g, red, B, M, R->q);
     if (threadIdx.x == 0) {
         R->B = B;
         R->M = M;

@@ -63,15 +63,21 @@ static std::string err_message(uint32_t bits)
 }
 
 // -------------------------------------------------------------- parameters
-// thr = floor(p * 2^32), p = 1 - exp(-2J/T) (Section 2, step (ii)), binary64.
-static uint32_t bond_threshold(double J, double T)
+// thr = floor(p * 2^32) in binary64 with p = 1 - exp(-2J/T) (Ising, Section
+// 2, step (ii)) or p = 1 - exp(-J/T) (q-state Potts, q > 0).
+static uint32_t bond_threshold(double J, double T, int q = 0)
 {
-    const double p = 1.0 - std::exp(-2.0 * J / T);
+    const double p = 1.0 - std::exp(-(q ? 1.0 : 2.0) * J / T);
     const double scaled = std::ldexp(p, 32);
     if (!(scaled > 0.0)) return 0u;
     if (scaled >= 4294967295.0) return 0xFFFFFFFFu;
     return (uint32_t)std::floor(scaled);
 }
+
+static bool valid_q(int q) { return q == 0 || (q >= 2 && q <= 127); }
+
+// Byte of a uniform start: Ising +1 / -1, Potts colour 0 / colour 1.
+static int start_byte(int q, int start) { return q ? (start > 0 ? 0x00 : 0x01) : (start > 0 ? 0x01 : 0xFF); }
 
 static wolff::Div make_div(uint32_t d)
 {
@@ -123,17 +129,23 @@ static uint64_t host_site_addr(const Geo& g, int dim, uint64_t i)
 }
 
 // Device spins (storage order) -> host spins (site order), and back.
-// Device bytes may carry member tags; bit 1 is the sign of every byte.
-static int copy_spins_out(const Geo& g, int dim, const int8_t* dev, int8_t* host, uint64_t n)
+// Ising bytes may carry member tags; bit 1 is the sign of every byte.
+// Potts bytes (q > 0) are the colours.
+static int copy_spins_out(const Geo& g, int dim, const int8_t* dev, int8_t* host, uint64_t n,
+                          int q = 0)
 {
     if (!g.tiled) {
         HIP_TRY(hipMemcpy(host, dev, n, hipMemcpyDeviceToHost));
-        for (uint64_t i = 0; i < n; ++i) host[i] = (host[i] & 2) ? -1 : 1;
+        if (!q)
+            for (uint64_t i = 0; i < n; ++i) host[i] = (host[i] & 2) ? -1 : 1;
         return WOLFF_OK;
     }
     std::vector<int8_t> tmp(n);
     HIP_TRY(hipMemcpy(tmp.data(), dev, n, hipMemcpyDeviceToHost));
-    for (uint64_t i = 0; i < n; ++i) host[i] = (tmp[host_site_addr(g, dim, i)] & 2) ? -1 : 1;
+    for (uint64_t i = 0; i < n; ++i) {
+        const int8_t b = tmp[host_site_addr(g, dim, i)];
+        host[i] = q ? b : ((b & 2) ? -1 : 1);
+    }
     return WOLFF_OK;
 }
 
@@ -248,6 +260,7 @@ struct EventPair {
 struct wolff_sim {
     int dim = 2;
     int L = 0;
+    int q = 0;                            // 0: Ising; q >= 2: q-state Potts
     uint64_t N = 0;
     double J = 1.0, T = 1.0;
     uint64_t seed = 0;
@@ -298,6 +311,7 @@ static constexpr double SMALL_CLUSTER = 16384.0;
 
 static int resolved_path(const wolff_sim* s)
 {
+    if (s->q) return WOLFF_PATH_SINGLE;                 // Potts: one-workgroup path only
     if (s->path != WOLFF_PATH_AUTO) return s->path;
     if (s->N < (1ull << 20)) return WOLFF_PATH_SINGLE;
     return (!s->measure && s->csize_mean >= 0.0 && s->csize_mean < SMALL_CLUSTER)
@@ -388,9 +402,10 @@ static int measure_now(wolff_sim* s)
     return WOLFF_OK;
 }
 
-extern "C" int wolff_create(int dim, int L, double J, double T, uint64_t seed, wolff_sim** out)
+static int create_sim(int dim, int L, int q, double J, double T, uint64_t seed, wolff_sim** out)
 {
     if (!out) return fail(WOLFF_EINVAL, "out is NULL");
+    if (!valid_q(q)) return fail(WOLFF_EINVAL, "q must be 2..127 (or 0 for Ising)");
     uint64_t N = 0;
     int rc = check_params(dim, L, J, T, &N);
     if (rc) return rc;
@@ -398,11 +413,12 @@ extern "C" int wolff_create(int dim, int L, double J, double T, uint64_t seed, w
     if (!s) return fail(WOLFF_ENOMEM, "host allocation failed");
     s->dim = dim;
     s->L = L;
+    s->q = q;
     s->N = N;
     s->J = J;
     s->T = T;
     s->seed = seed;
-    s->thr = bond_threshold(J, T);
+    s->thr = bond_threshold(J, T, q);
     s->geo = make_geo(dim, (uint32_t)L);
 
 #define CREATE_TRY(expr)                                                                \
@@ -431,10 +447,11 @@ extern "C" int wolff_create(int dim, int L, double J, double T, uint64_t seed, w
 
     hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((N + 255) / 256, 65536)),
                        dim3(256), 0, s->stream, s->S, s->geo, dim, (uint32_t)seed,
-                       (uint32_t)(seed >> 32));
+                       (uint32_t)(seed >> 32), (uint32_t)q);
     CREATE_TRY(hipGetLastError());
 
     Rep r{};
+    r.q = (uint32_t)q;
     r.S = s->S;
     r.ov = s->ov;
     r.rec = s->d_rec;
@@ -457,6 +474,18 @@ extern "C" int wolff_create(int dim, int L, double J, double T, uint64_t seed, w
 #undef CREATE_TRY
     *out = s;
     return WOLFF_OK;
+}
+
+extern "C" int wolff_create(int dim, int L, double J, double T, uint64_t seed, wolff_sim** out)
+{
+    return create_sim(dim, L, 0, J, T, seed, out);
+}
+
+extern "C" int wolff_create_potts(int dim, int L, int q, double J, double T, uint64_t seed,
+                                  wolff_sim** out)
+{
+    if (q == 0) return fail(WOLFF_EINVAL, "q must be 2..127");
+    return create_sim(dim, L, q, J, T, seed, out);
 }
 
 extern "C" int wolff_destroy(wolff_sim* s)
@@ -709,6 +738,8 @@ extern "C" int wolff_get_info(wolff_sim* s, wolff_info* out)
     out->seed = s->seed;
     out->threshold = s->thr;
     out->path = resolved_path(s);
+    out->q = s->q;
+    out->reserved = 0;
     out->t = r.t;
     out->mag = r.M;
     out->bond_sum = r.B;
@@ -721,7 +752,7 @@ extern "C" int wolff_get_spins(wolff_sim* s, int8_t* host, uint64_t n)
     if (!s || !host) return fail(WOLFF_EINVAL, "NULL argument");
     if (n != s->N) return fail(WOLFF_EINVAL, "n must equal the number of sites");
     HIP_TRY(hipStreamSynchronize(s->stream));
-    return copy_spins_out(s->geo, s->dim, s->S, host, n);
+    return copy_spins_out(s->geo, s->dim, s->S, host, n, s->q);
 }
 
 extern "C" int wolff_set_spins(wolff_sim* s, const int8_t* host, uint64_t n, uint64_t t)
@@ -729,8 +760,13 @@ extern "C" int wolff_set_spins(wolff_sim* s, const int8_t* host, uint64_t n, uin
     if (!s || !host) return fail(WOLFF_EINVAL, "NULL argument");
     if (n != s->N) return fail(WOLFF_EINVAL, "n must equal the number of sites");
     if (t > T_LIMIT) return fail(WOLFF_ERANGE, "t exceeds 2^32 - 2");
-    for (uint64_t i = 0; i < n; ++i)
-        if (host[i] != 1 && host[i] != -1) return fail(WOLFF_EINVAL, "spins must be +1 or -1");
+    if (s->q) {
+        for (uint64_t i = 0; i < n; ++i)
+            if (host[i] < 0 || host[i] >= s->q) return fail(WOLFF_EINVAL, "colours must be in [0, q)");
+    } else {
+        for (uint64_t i = 0; i < n; ++i)
+            if (host[i] != 1 && host[i] != -1) return fail(WOLFF_EINVAL, "spins must be +1 or -1");
+    }
     Rep r;
     int rc = pull_rep(s, &r);
     if (rc) return rc;
@@ -772,6 +808,7 @@ extern "C" int wolff_set_path(wolff_sim* s, int path, int workgroups)
     if (path != WOLFF_PATH_AUTO && path != WOLFF_PATH_SINGLE && path != WOLFF_PATH_TEAM)
         return fail(WOLFF_EINVAL, "unknown path");
     if (workgroups < 0 || workgroups > 65536) return fail(WOLFF_EINVAL, "bad workgroup count");
+    if (s->q && path == WOLFF_PATH_TEAM) return fail(WOLFF_EINVAL, "Potts lattices run on one workgroup");
     s->path = path;
     s->team_wgs = workgroups;
     return WOLFF_OK;
@@ -869,9 +906,10 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
             free_batch(b);
             return fail(rc, "job " + std::to_string(i) + ": " + g_last_error);
         }
-        if (jobs[i].start < -1 || jobs[i].start > 1 || (jobs[i].flags & ~WOLFF_JOB_UPDATE_ONLY) != 0) {
+        if (jobs[i].start < -1 || jobs[i].start > 1 || (jobs[i].flags & ~WOLFF_JOB_UPDATE_ONLY) != 0 ||
+            !valid_q(jobs[i].q)) {
             free_batch(b);
-            return fail(WOLFF_EINVAL, "job " + std::to_string(i) + ": bad start or flags field");
+            return fail(WOLFF_EINVAL, "job " + std::to_string(i) + ": bad start, flags or q field");
         }
         if (jobs[i].n_updates > T_LIMIT) {
             free_batch(b);
@@ -911,7 +949,8 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
         r.rec_count = 0;
         r.geo = make_geo(j.dim, (uint32_t)j.L);
         r.dim = j.dim;
-        r.thr = bond_threshold(j.J, j.T);
+        r.q = (uint32_t)j.q;
+        r.thr = bond_threshold(j.J, j.T, j.q);
         r.k0 = (uint32_t)j.seed;
         r.k1 = (uint32_t)(j.seed >> 32);
         r.t = 0;
@@ -919,10 +958,10 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
         r.measure = (j.flags & WOLFF_JOB_UPDATE_ONLY) ? 0u : 1u;
         if (j.start == 0) {
             hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((Ns[i] + 255) / 256, 65536)),
-                               dim3(256), 0, b->stream, r.S, r.geo, j.dim, r.k0, r.k1);
+                               dim3(256), 0, b->stream, r.S, r.geo, j.dim, r.k0, r.k1, r.q);
             BATCH_TRY(hipGetLastError());
         } else {
-            BATCH_TRY(hipMemsetAsync(r.S, j.start > 0 ? 0x01 : 0xFF, Ns[i], b->stream));
+            BATCH_TRY(hipMemsetAsync(r.S, start_byte(j.q, j.start), Ns[i], b->stream));
         }
         b->left.push_back(j.n_updates);
         b->t.push_back(0);
@@ -1083,7 +1122,7 @@ extern "C" int wolff_batch_get_spins(wolff_batch* b, int job, int8_t* host, uint
     const Rep& r = b->reps[job];
     if (n != r.geo.N) return fail(WOLFF_EINVAL, "n must equal the number of sites");
     HIP_TRY(hipStreamSynchronize(b->stream));
-    return copy_spins_out(r.geo, r.dim, r.S, host, n);
+    return copy_spins_out(r.geo, r.dim, r.S, host, n, (int)r.q);
 }
 
 // ================================================================== server
@@ -1208,8 +1247,9 @@ extern "C" int wolff_server_submit(wolff_server* v, const wolff_job* job, uint64
     uint64_t N = 0;
     int rc = check_params(job->dim, job->L, job->J, job->T, &N);
     if (rc) return rc;
-    if (job->start < -1 || job->start > 1 || (job->flags & ~WOLFF_JOB_UPDATE_ONLY) != 0)
-        return fail(WOLFF_EINVAL, "bad start or flags field");
+    if (job->start < -1 || job->start > 1 || (job->flags & ~WOLFF_JOB_UPDATE_ONLY) != 0 ||
+        !valid_q(job->q))
+        return fail(WOLFF_EINVAL, "bad start, flags or q field");
     if (job->n_updates > T_LIMIT) return fail(WOLFF_ERANGE, "too many updates");
     SrvJob j;
     j.spec = *job;
@@ -1240,10 +1280,11 @@ static int server_admit(wolff_server* v)
         if (j.spec.start == 0) {
             hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((j.N + 255) / 256, 65536)),
                                dim3(256), 0, v->stream, S, make_geo(j.spec.dim, (uint32_t)j.spec.L),
-                               j.spec.dim, (uint32_t)j.spec.seed, (uint32_t)(j.spec.seed >> 32));
+                               j.spec.dim, (uint32_t)j.spec.seed, (uint32_t)(j.spec.seed >> 32),
+                               (uint32_t)j.spec.q);
             HIP_TRY(hipGetLastError());
         } else {
-            HIP_TRY(hipMemsetAsync(S, j.spec.start > 0 ? 0x01 : 0xFF, j.N, v->stream));
+            HIP_TRY(hipMemsetAsync(S, start_byte(j.spec.q, j.spec.start), j.N, v->stream));
         }
         Rep& r = j.rep;
         r = Rep{};
@@ -1253,7 +1294,8 @@ static int server_admit(wolff_server* v)
         r.rec_count = 0;
         r.geo = make_geo(j.spec.dim, (uint32_t)j.spec.L);
         r.dim = j.spec.dim;
-        r.thr = bond_threshold(j.spec.J, j.spec.T);
+        r.q = (uint32_t)j.spec.q;
+        r.thr = bond_threshold(j.spec.J, j.spec.T, j.spec.q);
         r.k0 = (uint32_t)j.spec.seed;
         r.k1 = (uint32_t)(j.spec.seed >> 32);
         r.t = 0;

@@ -31,6 +31,7 @@ class Job:
     n_updates: int
     J: float = J
     arrival_s: float = 0.0
+    q: int = 0                  # 0: Ising; q >= 2: q-state Potts
 
     @property
     def n_sites(self) -> int:

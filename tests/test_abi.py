@@ -63,3 +63,11 @@ def test_null_handles_are_rejected(lib):
     assert lib.wolff_create(2, 8, 1.0, 2.0, 1, None) == binding.EINVAL
     assert lib.wolff_destroy(None) == binding.OK
     assert lib.wolff_batch_create(None, 0, None) == binding.EINVAL
+
+
+@pytest.mark.parametrize("q", [0, 1, -3, 128, 1000])
+def test_create_potts_rejects_bad_q(lib, q):
+    # parameters are checked before any device call
+    h = ctypes.c_void_p()
+    assert lib.wolff_create_potts(2, 8, q, 1.0, 1.0, 1, ctypes.byref(h)) == binding.EINVAL
+    assert not h.value
