@@ -76,15 +76,15 @@ def ordered_start(n_sites: int) -> np.ndarray:
 
 
 def plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered=True, measure=True,
-              warm_sweeps=0.0):
+              warm_sweeps=0.0, q=0):
     """Plain one-lattice path: warmup updates (and, with warm_sweeps, more
     until the flipped spins add up to that many lattice sweeps), then
     `steps` timed updates."""
     import torch
-    sim = binding.Simulation(dim, L, 1.0, T, seed)
+    sim = binding.Simulation(dim, L, 1.0, T, seed, q=q)
     sim.set_measure(measure)
     if start_ordered:
-        sim.set_spins(ordered_start(L ** dim), 0)
+        sim.set_spins(np.zeros(L ** dim, dtype=np.int8) if q else ordered_start(L ** dim), 0)
     t0 = time.time()
     sim.run(warmup)
     sim.synchronize()
@@ -129,7 +129,7 @@ def plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered=True, measu
         % (dim, L, steps, wall, added / max(steps, 1), added / wall,
            grow_ms / max(prof["grow_launches"], 1)))
     return {
-        "dim": dim, "L": L, "T": T, "seed": seed, "warmup": warmup, "steps": steps,
+        "dim": dim, "L": L, "T": T, "seed": seed, "q": q, "warmup": warmup, "steps": steps,
         "measurement": bool(measure),
         "wall_s": wall, "added": added, "added_per_s": added / wall,
         "updates_per_s": steps / wall, "mean_csize": added / max(steps, 1),
@@ -140,21 +140,22 @@ def plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered=True, measu
     }
 
 
-def batch_leg(binding, workloads, dim, L, n_rep, warmup, steps, wg=None, q=None):
+def batch_leg(binding, workloads, dim, L, n_rep, warmup, steps, wg=None, qe=None, potts_q=0):
     """Batched persistent form: n_rep same-shape replicas at T_c, one launch
     per run; warmup updates, then `steps` timed updates of every replica.
-    Tile sizes come from the autotuner unless given."""
-    jobs = workloads.same_shape_jobs(dim, L, n_rep, warmup + steps)
+    Tile sizes (wg, LDS ring entries qe) come from the autotuner unless
+    given; potts_q >= 2: the q-state Potts model."""
+    jobs = workloads.same_shape_jobs(dim, L, n_rep, warmup + steps, q=potts_q)
     tuned = None
-    if wg is None or q is None:
+    if wg is None or qe is None:
         from paper_1110_0899_amd import autotune
         # tune on the replica count of the run: the best tiles depend on how
         # full the device is
-        tjobs = workloads.same_shape_jobs(dim, L, n_rep, 16)
+        tjobs = workloads.same_shape_jobs(dim, L, n_rep, 16, q=potts_q)
         tuned = autotune.tune(tjobs, warm=8, timed=4, start=1, log=log)
-        wg, q = tuned["wg"], tuned["queue_entries"]
+        wg, qe = tuned["wg"], tuned["queue_entries"]
     b = binding.Batch(jobs, start=1)
-    b.set_tiles(wg, q)
+    b.set_tiles(wg, qe)
     b.set_measure(True)
     t0 = time.time()
     b.run(warmup)
@@ -174,8 +175,8 @@ def batch_leg(binding, workloads, dim, L, n_rep, warmup, steps, wg=None, q=None)
     log("batch %dD L=%d x%d: %d updates each in %.2f s (kernel %.2f s), %.3e added/s"
         % (dim, L, n_rep, steps, wall, kernel_s, added / kernel_s))
     return {
-        "dim": dim, "L": L, "replicas": n_rep, "warmup": warmup, "steps": steps, "wg": wg,
-        "queue_entries": q, "wall_s": wall, "kernel_s": kernel_s, "added": added,
+        "dim": dim, "L": L, "q": potts_q, "replicas": n_rep, "warmup": warmup, "steps": steps,
+        "wg": wg, "queue_entries": qe, "wall_s": wall, "kernel_s": kernel_s, "added": added,
         "added_per_s": added / wall, "updates_per_s": n_rep * steps / wall,
         "mean_csize": added / (n_rep * steps),
         "kernel_GBs_algorithmic": BYTES_PER_ADDED[dim] * added / kernel_s / 1e9,
@@ -299,6 +300,21 @@ def temps_leg(binding, workloads, cpu_seconds):
     return rows
 
 
+def potts_leg(binding, workloads, args):
+    """The q-state Potts extension (q = 3 at the square-lattice T_c): the
+    plain one-workgroup path on L = 1024 with the oracle beside it, and the
+    batched form on 1536 replicas of L = 4096 (tiles from the autotuner)."""
+    q = 3
+    T = workloads.potts_tc_2d(q)
+    p = plain_leg(binding, 2, 1024, T, 2, 300, 300, q=q)
+    cpu = cpu_baseline(p, args.sweep_cpu_seconds)
+    b = batch_leg(binding, workloads, 2, 4096, args.batch_replicas, args.batch_warmup,
+                  args.batch_steps, potts_q=q)
+    return {"q": q, "T": T,
+            "plain_2d_L1024": {k: v for k, v in p.items() if k not in ("records", "checkpoint")},
+            "plain_cpu_oracle": cpu, "batch_2d_L4096": b}
+
+
 def copy_peak_gbs(reps=5):
     """Device-to-device copy bandwidth (read + write bytes / time), 2 GiB."""
     import torch
@@ -340,15 +356,18 @@ def serve_leg(workloads, quantum_ms=5.0, n_jobs=2000, max_wall_s=20.0):
 def cpu_baseline(leg, budget_s=15.0):
     """The CPU oracle (one core) replaying updates from the GPU checkpoint."""
     import oracle
-    dim, L, T, seed = leg["dim"], leg["L"], leg["T"], leg["seed"]
-    thr = oracle.threshold(1.0, T)
+    dim, L, T, seed, q = leg["dim"], leg["L"], leg["T"], leg["seed"], leg.get("q", 0)
+    thr = oracle.potts_threshold(1.0, T) if q else oracle.threshold(1.0, T)
     S = leg["checkpoint"].copy()
     t = leg["t_ckpt"]
     gpu = leg["records"]
     done, added, match = 0, 0, True
     a = time.perf_counter()
     while done < len(gpu) and time.perf_counter() - a < budget_s:
-        rec = oracle.run(dim, L, thr, seed, t + done, 1, S)
+        if q:
+            rec = oracle.potts_run(dim, L, q, thr, seed, t + done, 1, S)
+        else:
+            rec = oracle.run(dim, L, thr, seed, t + done, 1, S)
         g = gpu[done]
         match &= (int(g["bond_sum"]), int(g["mag"]), int(g["csize"])) == tuple(int(v) for v in rec[0])
         added += int(rec[0, 2])
@@ -386,7 +405,7 @@ def profile_only(args, binding, workloads):
         wg, q = (int(v) for v in args.tiles.split(","))
         dim, L = (2, 4096) if leg == "batch2d" else (3, 256)
         r = batch_leg(binding, workloads, dim, L, args.batch_replicas, args.warmup,
-                      args.batch_steps, wg=wg, q=q)
+                      args.batch_steps, wg=wg, qe=q)
     else:
         raise SystemExit("unknown leg %s" % leg)
     r = {k: v for k, v in r.items() if k not in ("records", "checkpoint")}
@@ -407,8 +426,8 @@ def main():
     ap.add_argument("--batch-warmup", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--sweep-cpu-seconds", type=float, default=4.0,
-                    help="oracle time per point of the sweeps (legs sizes, temps; run without "
-                         "plain2d, they print their own JSON line)")
+                    help="oracle time per point of the sweeps (legs sizes, temps, potts; run "
+                         "without plain2d, they print their own JSON line)")
     ap.add_argument("--tiles", default="512,2048",
                     help="workgroup size, LDS ring entries of a profiled batch leg (the full "
                          "benchmark takes them from the autotuner)")
@@ -441,6 +460,8 @@ def main():
             out["sizes"] = sizes_leg(binding, workloads, args.sweep_cpu_seconds)
         if "temps" in legs:
             out["temps"] = temps_leg(binding, workloads, args.sweep_cpu_seconds)
+        if "potts" in legs:
+            out["potts"] = potts_leg(binding, workloads, args)
         print(json.dumps(out), flush=True)
         return
 

@@ -6,7 +6,8 @@ updates (the random stream does not depend on the tiles, so the work is
 identical and the results bit-equal), and the candidate with the shortest
 kernel time wins.  Results are cached in a JSON file keyed by
 (GPU architecture, dim, log2 of L rounded up, replica count class); the file
-is $WOLFF_TUNE_CACHE or ~/.cache/wolff_mi355x_tune.json.
+is $WOLFF_TUNE_CACHE or ~/.cache/wolff_mi355x_tune.json (Potts replica sets
+have keys of their own).
 """
 from __future__ import annotations
 
@@ -33,9 +34,10 @@ def _arch() -> str:
         return "unknown"
 
 
-def key(dim: int, L: int, n_replicas: int) -> str:
-    return "%s|d%d|L2^%d|B2^%d" % (_arch(), dim, math.ceil(math.log2(max(L, 2))),
-                                   math.ceil(math.log2(max(n_replicas, 1))))
+def key(dim: int, L: int, n_replicas: int, q: int = 0) -> str:
+    k = "%s|d%d|L2^%d|B2^%d" % (_arch(), dim, math.ceil(math.log2(max(L, 2))),
+                                math.ceil(math.log2(max(n_replicas, 1))))
+    return k + ("|potts" if q else "")
 
 
 def _load_cache() -> dict:
@@ -75,7 +77,7 @@ def tune(jobs, warm: int = 4, timed: int = 4, start: int = 1, candidates=None,
          use_cache: bool = True, log=None) -> dict:
     """Best (wg, queue_entries) for a list of same-class jobs."""
     j0 = jobs[0]
-    k = key(j0.dim, j0.L, len(jobs))
+    k = key(j0.dim, j0.L, len(jobs), getattr(j0, "q", 0))
     if use_cache:
         hit = _load_cache().get(k)
         if hit:

@@ -67,11 +67,19 @@ def c4_jobs(n_updates: int = 10_000) -> list[Job]:
     return jobs
 
 
-def same_shape_jobs(dim: int, L: int, n_replicas: int, n_updates: int) -> list[Job]:
-    """n_replicas copies of one lattice at its critical temperature with
-    per-replica seeds 0x48000000 + r."""
-    T = TC_2D if dim == 2 else T_3D
-    return [Job(dim, L, T, 0x48000000 + r, n_updates) for r in range(n_replicas)]
+def potts_tc_2d(q: int) -> float:
+    """Critical temperature of the square-lattice q-state Potts model (J = 1):
+    T_c = 1 / ln(1 + sqrt q) (self-duality)."""
+    return 1.0 / math.log(1.0 + math.sqrt(q))
+
+
+def same_shape_jobs(dim: int, L: int, n_replicas: int, n_updates: int, q: int = 0,
+                    T: float | None = None) -> list[Job]:
+    """n_replicas copies of one lattice (at its critical temperature unless
+    T is given) with per-replica seeds 0x48000000 + r; q >= 2: Potts."""
+    if T is None:
+        T = (potts_tc_2d(q) if q else TC_2D) if dim == 2 else T_3D
+    return [Job(dim, L, T, 0x48000000 + r, n_updates, q=q) for r in range(n_replicas)]
 
 
 def c5_stream(n_jobs: int = 2000, rate_per_s: float = 100.0, seed: int = 5) -> list[Job]:
