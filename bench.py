@@ -8,7 +8,7 @@ workload's lattice.  The headline workload is the square lattice L = 4096 at
 T_c = 2/ln(1+sqrt 2) through the plain one-lattice launch path; the other
 legs are reported under "extra": simple-cubic L = 256, both plain lattices
 in "update only" mode, the L = 32 latency case with the oracle on all of it,
-the batched persistent form on 1536 replicas of each lattice, the mixed
+the batched persistent form on 2048 replicas of each lattice, the mixed
 replica set, the serving stream, and a device-copy bandwidth for the
 roofline.  Inputs are synthetic (seeded, no dataset).
 
@@ -303,7 +303,7 @@ def temps_leg(binding, workloads, cpu_seconds):
 def potts_leg(binding, workloads, args):
     """The q-state Potts extension (q = 3 at the square-lattice T_c): the
     plain one-workgroup path on L = 1024 with the oracle beside it, and the
-    batched form on 1536 replicas of L = 4096 (tiles from the autotuner)."""
+    batched form on --batch-replicas replicas of L = 4096 (tiles from the autotuner)."""
     q = 3
     T = workloads.potts_tc_2d(q)
     p = plain_leg(binding, 2, 1024, T, 2, 300, 300, q=q)
@@ -421,7 +421,7 @@ def main():
     ap.add_argument("--legs", default="plain2d,plain3d,updateonly,c1,batch2d,batch3d,c4,serve")
     ap.add_argument("--c4-updates", type=int, default=10000,
                     help="updates per replica of the mixed C4 batch")
-    ap.add_argument("--batch-replicas", type=int, default=1536)
+    ap.add_argument("--batch-replicas", type=int, default=2048)
     ap.add_argument("--batch-steps", type=int, default=8)
     ap.add_argument("--batch-warmup", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

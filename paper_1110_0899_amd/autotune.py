@@ -18,7 +18,7 @@ import time
 
 from . import binding
 
-CANDIDATES = [(128, 2048), (256, 2048), (256, 4096), (512, 2048), (512, 4096)]
+CANDIDATES = [(128, 2048), (256, 2048), (256, 4096), (512, 2048), (512, 4096), (1024, 4096)]
 
 
 def cache_path() -> str:
