@@ -1,16 +1,17 @@
 // gfx950 kernels of the Wolff single-cluster update.
 //
-// Two growth paths share the per-site expansion below:
+// Two growth paths share the bond keying and the per-site neighbour logic:
 //  * one workgroup per lattice (batch_kernel): the frontier lives in an LDS
 //    ring (spilling to a global overflow stack when it outgrows it); the
-//    workgroup runs every update of its lattice inside one launch.  Claims
-//    are workgroup-scope atomics because no other workgroup touches the
-//    lattice during the launch.  The same kernel runs one replica (the plain
-//    path for small lattices) or thousands (the batched form).
-//  * a team of workgroups per lattice (team_kernel, one launch per update):
-//    each workgroup expands from its own LDS queue and trades work through a
-//    tagged global queue with atomic head/tail counters and a pending count
-//    that decides termination; claims are agent-scope atomics.
+//    workgroup runs every update of its lattice inside one launch.  Because
+//    no other workgroup touches the lattice during the launch, claims are
+//    settled in an LDS hash table and written with plain byte stores.  The
+//    same kernel runs one replica (single lattices) or thousands (the batched
+//    form and the serving loop), Ising or q-state Potts.
+//  * a team of workgroups per lattice (team_kernel, one launch per update,
+//    Ising only): each workgroup expands from its own LDS queue and trades
+//    work through a tagged global queue with atomic head/tail counters and a
+//    pending count that decides termination; claims are agent-scope atomics.
 #pragma once
 
 #include "wolff_device.h"

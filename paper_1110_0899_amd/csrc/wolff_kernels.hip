@@ -14,7 +14,6 @@ constexpr uint32_t ERR_BOND = 4u;         // bond-sum recount != tracked value
 // Bound on the polls of one team wait (each poll is at least ~100 ns, so the
 // bound is seconds, far above any legitimate wait).
 constexpr uint32_t TEAM_SPIN_LIMIT = 1u << 26;
-constexpr int SCOPE_WG = __HIP_MEMORY_SCOPE_WORKGROUP;
 constexpr int SCOPE_AGENT = __HIP_MEMORY_SCOPE_AGENT;
 
 // --------------------------------------------------------------- expansion
@@ -499,6 +498,7 @@ __device__ __forceinline__ void clear_tags_wg(int8_t* S, uint32_t N)
 // the lattice's global overflow stack and come back when the ring runs low.
 // Items are appended in whole steps: ballot/mbcnt inside each wave, a prefix
 // over the waves' counts in LDS, one store per new site.
+
 // Workgroup-shared control words of the one-workgroup path.
 struct WgCtl {
     int s0;                 // seed spin (Ising) or colour (Potts) of the current update
@@ -515,6 +515,12 @@ __device__ __forceinline__ uint32_t budget_spent(const WgCtl* c, uint64_t budget
     return (budget != 0u && wall_clock64() - c->t_start >= budget) ? 1u : 0u;
 }
 
+// Up to max_updates (0: all left) updates of replica R, stopping early at an
+// update boundary once the launch's time budget is spent.  Per update: seed
+// site and seed spin/colour (step (i)), growth steps until the ring and the
+// overflow stack are empty (steps (ii)-(iv)), the flip done by the claims,
+// M updated exactly, B updated from the cluster (even-L Ising with
+// measurement) or recounted over the lattice, and one record (step (v)).
 template <int WG, int DIM>
 __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t budget, uint32_t qmask,
                         uint32_t* q, uint32_t* wave_cnt, long long* red, WgCtl* ctl)
@@ -699,8 +705,9 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
 // Persistent batched form: workgroup w starts with replica order[w] and then
 // takes order[gridDim.x + atomicAdd(next)] until the list or the time budget
 // (wall-clock ticks, 0 = none) is exhausted.  A replica is only ever
-// advanced by one workgroup per launch, so its claims are workgroup-scope;
-// the kernel boundary publishes its state to the next launch.
+// advanced by one workgroup per launch, so its claims need no device-scope
+// atomics (they are settled in LDS); the kernel boundary publishes its state
+// to the next launch.
 template <int WG, int DIMS>
 __global__ __launch_bounds__(WG) void batch_kernel(Rep* reps, const uint32_t* order,
                                                    uint32_t n_reps, uint32_t* next,
