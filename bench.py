@@ -422,7 +422,7 @@ def main():
     ap.add_argument("--c4-updates", type=int, default=10000,
                     help="updates per replica of the mixed C4 batch")
     ap.add_argument("--batch-replicas", type=int, default=2048)
-    ap.add_argument("--batch-steps", type=int, default=8)
+    ap.add_argument("--batch-steps", type=int, default=32)
     ap.add_argument("--batch-warmup", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--sweep-cpu-seconds", type=float, default=4.0,

@@ -159,7 +159,8 @@ int wolff_set_stream(wolff_sim *s, void *hip_stream);
 int wolff_set_path(wolff_sim *s, int path, int workgroups);
 
 /* Workgroup size and LDS frontier ring entries of the one-workgroup path
- * (same ranges as wolff_batch_set_tiles).  Default 256 and 2048. */
+ * (same ranges as wolff_batch_set_tiles).  Default: 2048 entries and 64
+ * threads up to 4096 sites, 128 up to 16384, 256 above. */
 int wolff_set_tiles(wolff_sim *s, int wg, int queue_entries);
 
 /* Team path: replay a captured HIP graph of `chunk` updates (the seed,
