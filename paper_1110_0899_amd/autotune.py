@@ -18,7 +18,10 @@ import time
 
 from . import binding
 
-CANDIDATES = [(128, 2048), (256, 2048), (256, 4096), (512, 2048), (512, 4096), (1024, 4096)]
+# (1024, 4096) is left out: in the tuner's short runs from the ordered start
+# it can look best for 3D L=256 while it is ~20 % slower than (512, 2048)
+# over a thermalised window on MI355X.
+CANDIDATES = [(128, 2048), (256, 2048), (256, 4096), (512, 2048), (512, 4096)]
 
 
 def cache_path() -> str:
