@@ -301,18 +301,22 @@ def temps_leg(binding, workloads, cpu_seconds):
 
 
 def potts_leg(binding, workloads, args):
-    """The q-state Potts extension (q = 3 at the square-lattice T_c): the
-    plain one-workgroup path on L = 1024 with the oracle beside it, and the
-    batched form on --batch-replicas replicas of L = 4096 (tiles from the autotuner)."""
+    """The q-state Potts extension (q = 3 at the square-lattice T_c): one
+    lattice of L = 1024 with the oracle beside it and one of L = 4096 (both
+    on the default growth path), and the batched form on --batch-replicas
+    replicas of L = 4096 (tiles from the autotuner)."""
     q = 3
     T = workloads.potts_tc_2d(q)
     p = plain_leg(binding, 2, 1024, T, 2, 300, 300, q=q)
     cpu = cpu_baseline(p, args.sweep_cpu_seconds)
+    p4 = plain_leg(binding, 2, 4096, T, 3, 200, 100, q=q)
     b = batch_leg(binding, workloads, 2, 4096, args.batch_replicas, args.batch_warmup,
                   args.batch_steps, potts_q=q)
     return {"q": q, "T": T,
             "plain_2d_L1024": {k: v for k, v in p.items() if k not in ("records", "checkpoint")},
-            "plain_cpu_oracle": cpu, "batch_2d_L4096": b}
+            "plain_cpu_oracle": cpu,
+            "plain_2d_L4096": {k: v for k, v in p4.items() if k not in ("records", "checkpoint")},
+            "batch_2d_L4096": b}
 
 
 def copy_peak_gbs(reps=5):

@@ -100,9 +100,9 @@ int wolff_create(int dim, int L, double J, double T, uint64_t seed, wolff_sim **
  * mag = q (number of colour-0 sites) - N.  Spins are colours (int8) in
  * wolff_get_spins / wolff_set_spins.  With q = 2 and J twice the Ising J
  * the update, spins (colour 0 = +1) and records are the Ising ones.
- * Potts lattices run on the one-workgroup path (WOLFF_PATH_TEAM is
- * WOLFF_EINVAL) with a lattice recount per measured update.  Otherwise as
- * wolff_create. */
+ * Both growth paths serve Potts lattices (the team path claims a site with
+ * a compare-and-swap of its colour); the bond sum is recounted over the
+ * lattice after every measured update.  Otherwise as wolff_create. */
 int wolff_create_potts(int dim, int L, int q, double J, double T, uint64_t seed,
                        wolff_sim **out);
 

@@ -238,6 +238,29 @@ __device__ __forceinline__ bool claim(int8_t* S, uint32_t k, int s0)
     }
 }
 
+// Potts claim of byte k (colour s0 -> c, c != s0) for several workgroups:
+// a compare-and-swap of the aligned word, retried while only other bytes of
+// the word change; exactly one caller finds the byte equal to s0.  Each byte
+// of a word changes at most once per update, so the loop ends after at most
+// four attempts.
+template <int SCOPE>
+__device__ __forceinline__ bool claim_colour(int8_t* S, uint32_t k, uint32_t s0, uint32_t c)
+{
+    uint32_t* w = reinterpret_cast<uint32_t*>(S) + (k >> 2);
+    const uint32_t sh = (k & 3u) * 8u;
+    uint32_t old = __hip_atomic_load(w, __ATOMIC_RELAXED, SCOPE);
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        if (((old >> sh) & 0xFFu) != s0) return false;
+        const uint32_t nw = (old & ~(0xFFu << sh)) | (c << sh);
+        uint32_t expected = old;
+        if (__hip_atomic_compare_exchange_strong(w, &expected, nw, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, SCOPE))
+            return true;
+        old = expected;
+    }
+    return false;   // unreachable (at most four changes of the word per update)
+}
+
 // ------------------------------------------------------------ member tags
 // The one-workgroup path can instead tag the members of the current cluster,
 // which is what lets it update the bond sum from the cluster alone.  A plain

@@ -8,10 +8,11 @@
 //    settled in an LDS hash table and written with plain byte stores.  The
 //    same kernel runs one replica (single lattices) or thousands (the batched
 //    form and the serving loop), Ising or q-state Potts.
-//  * a team of workgroups per lattice (team_kernel, one launch per update,
-//    Ising only): each workgroup expands from its own LDS queue and trades
-//    work through a tagged global queue with atomic head/tail counters and a
-//    pending count that decides termination; claims are agent-scope atomics.
+//  * a team of workgroups per lattice (team_kernel, one launch per update):
+//    each workgroup expands from its own LDS queue and trades work through a
+//    tagged global queue with atomic head/tail counters and a pending count
+//    that decides termination; claims are agent-scope atomics (Ising: an
+//    OR/AND on the spin's word, Potts: a compare-and-swap of the colour).
 #pragma once
 
 #include "wolff_device.h"
@@ -50,11 +51,11 @@ struct TeamCtl {
     uint32_t exited;        // workgroups done with this update
     uint32_t epoch;         // tag of this update's queue entries (never 0)
     uint32_t s;             // seed site
-    int32_t s0;             // seed spin before the update
-    uint32_t pad;
+    int32_t s0;             // seed spin (Ising) or colour (Potts) before the update
+    int32_t cb;             // Potts: the cluster's new colour
     unsigned long long csize;
-    long long acc_diff;     // measurement: differing bonds
-    long long acc_neg;      // measurement: negative spins
+    long long acc_diff;     // measurement: differing bonds (Potts: equal bonds)
+    long long acc_neg;      // measurement: negative spins (Potts: colour-0 sites)
     uint32_t blocks_done;
     uint32_t pad2;
 };

@@ -46,12 +46,13 @@ __device__ __forceinline__ void bond_words(uint32_t j, const uint32_t nb[2 * DIM
     }
 }
 
-// Team path: spins are plain bytes and a claim is the atomic flip.
+// Team path: spins are plain bytes and a claim is the atomic flip (Ising) or
+// the colour compare-and-swap (Potts, pq > 0, new colour c).
 template <int DIM, int SCOPE>
 __device__ __forceinline__ void expand_site(bool active, uint32_t j, const Geo& g, int8_t* S,
                                             int s0, uint32_t thr, uint32_t k0, uint32_t k1,
                                             uint32_t t, uint32_t s, uint32_t nb[2 * DIM],
-                                            bool won[2 * DIM])
+                                            bool won[2 * DIM], uint32_t pq = 0u, uint32_t c = 0u)
 {
     if (!active) j = 0u;
     uint32_t sa[2 * DIM];
@@ -64,7 +65,8 @@ __device__ __forceinline__ void expand_site(bool active, uint32_t j, const Geo& 
 #pragma unroll
     for (int m = 0; m < 2 * DIM; ++m) {
         const uint32_t r = (m & 1) ? rm[m / 2] : rp[m / 2];
-        won[m] = active && b[m] == s0 && r < thr && claim<SCOPE>(S, sa[m], s0);
+        const bool act = active && b[m] == s0 && r < thr;
+        won[m] = act && (pq ? claim_colour<SCOPE>(S, sa[m], (uint32_t)s0, c) : claim<SCOPE>(S, sa[m], s0));
     }
 }
 
@@ -817,12 +819,19 @@ __global__ void team_seed_kernel(Rep* R, TeamCtl* ctl, unsigned long long* gq)
     int8_t* S = R->S;
     const uint32_t a = (R->dim == 2) ? site_addr<2>(g, s) : site_addr<3>(g, s);
     const int s0 = S[a];
-    claim<SCOPE_AGENT>(S, a, s0);
+    int c = 0;
+    if (R->q) {                                   // Potts: the cluster's new colour
+        c = (int)potts_new_colour(R->k0, R->k1, t, R->q, (uint32_t)s0);
+        S[a] = (int8_t)c;
+    } else {
+        claim<SCOPE_AGENT>(S, a, s0);
+    }
     uint32_t epoch = ctl->epoch + 1u;
     if (epoch == 0u) epoch = 1u;
     ctl->epoch = epoch;
     ctl->s = s;
     ctl->s0 = s0;
+    ctl->cb = c;
     ctl->head = 0u;
     ctl->tail = 1u;
     ctl->pending = 1;
@@ -853,6 +862,8 @@ __global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned
     const uint32_t s = ctl->s;
     const int s0 = ctl->s0;
     const uint32_t epoch = ctl->epoch;
+    const uint32_t pq = R->q;
+    const uint32_t cnew = (uint32_t)ctl->cb;
 
     uint32_t head = 0u, tail = 0u;           // local ring
     uint64_t my_claims = 0u;
@@ -927,7 +938,7 @@ __global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned
 
         uint32_t nb[2 * DIM];
         bool won[2 * DIM];
-        expand_site<DIM, SCOPE_AGENT>(active, j, g, S, s0, thr, k0, k1, t, s, nb, won);
+        expand_site<DIM, SCOPE_AGENT>(active, j, g, S, s0, thr, k0, k1, t, s, nb, won, pq, cnew);
         uint32_t pos[2 * DIM];
         const uint32_t wtot = wave_compact<DIM>(won, pos);
         if (lane == 0) wave_cnt[wv] = wtot;
@@ -978,7 +989,9 @@ __global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned
         if (prev == gridDim.x - 1u) {
             const unsigned long long csize =
                 __hip_atomic_load(&ctl->csize, __ATOMIC_RELAXED, SCOPE_AGENT);
-            const int64_t M = R->M - 2 * (int64_t)s0 * (int64_t)csize;
+            const int64_t M = pq ? R->M + (int64_t)pq * (int64_t)csize *
+                                              ((int64_t)(cnew == 0u) - (int64_t)(s0 == 0))
+                                 : R->M - 2 * (int64_t)s0 * (int64_t)csize;
             R->M = M;
             if (R->measure == 0u) {
                 R->b_valid = 0u;
@@ -1001,8 +1014,12 @@ __global__ __launch_bounds__(256) void measure_grid_kernel(Rep* R, TeamCtl* ctl)
     constexpr int WG = 256, NW = WG / WAVE;
     __shared__ long long red[2 * NW];
     const Geo g = R->geo;
+    const uint32_t pq = R->q;
     uint64_t d, neg;
-    lattice_counts<DIM, 4>(R->S, g, blockIdx.x * WG + threadIdx.x, gridDim.x * WG, d, neg);
+    if (pq)
+        lattice_counts<DIM, 4, true>(R->S, g, blockIdx.x * WG + threadIdx.x, gridDim.x * WG, d, neg);
+    else
+        lattice_counts<DIM, 4, false>(R->S, g, blockIdx.x * WG + threadIdx.x, gridDim.x * WG, d, neg);
     d = wave_sum_u64(d);
     neg = wave_sum_u64(neg);
     if ((threadIdx.x & (WAVE - 1)) == 0) {
@@ -1023,8 +1040,9 @@ __global__ __launch_bounds__(256) void measure_grid_kernel(Rep* R, TeamCtl* ctl)
         if (prev == gridDim.x - 1u) {
             const long long td = __hip_atomic_load(&ctl->acc_diff, __ATOMIC_RELAXED, SCOPE_AGENT);
             const long long tn = __hip_atomic_load(&ctl->acc_neg, __ATOMIC_RELAXED, SCOPE_AGENT);
-            const int64_t B = (int64_t)DIM * (int64_t)g.N - 2 * (int64_t)td;
-            const int64_t Mm = (int64_t)g.N - 2 * (int64_t)tn;
+            const int64_t B = pq ? (int64_t)pq * td - (int64_t)DIM * (int64_t)g.N
+                                 : (int64_t)DIM * (int64_t)g.N - 2 * (int64_t)td;
+            const int64_t Mm = pq ? (int64_t)pq * tn - (int64_t)g.N : (int64_t)g.N - 2 * (int64_t)tn;
             const int64_t M = R->M;
             if (Mm != M) R->err |= ERR_MAG;
             R->B = B;

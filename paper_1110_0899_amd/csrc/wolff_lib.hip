@@ -311,7 +311,6 @@ static constexpr double SMALL_CLUSTER = 16384.0;
 
 static int resolved_path(const wolff_sim* s)
 {
-    if (s->q) return WOLFF_PATH_SINGLE;                 // Potts: one-workgroup path only
     if (s->path != WOLFF_PATH_AUTO) return s->path;
     if (s->N < (1ull << 20)) return WOLFF_PATH_SINGLE;
     return (!s->measure && s->csize_mean >= 0.0 && s->csize_mean < SMALL_CLUSTER)
@@ -659,7 +658,7 @@ extern "C" int wolff_run(wolff_sim* s, uint64_t n)
         for (; u < n; ++u)
             if ((rc = run_team_update(s))) return rc;
     } else {
-        if (s->measure) s->tagged = true;       // measured updates leave member tags
+        if (s->measure && !s->q) s->tagged = true;   // measured Ising updates leave member tags
         // one workgroup runs the updates; chunk so that one launch stays short
         // (about 2^26 sites of work: the expected cluster, plus the lattice
         // recount every 32 measured updates), at most 65536 updates
@@ -812,7 +811,6 @@ extern "C" int wolff_set_path(wolff_sim* s, int path, int workgroups)
     if (path != WOLFF_PATH_AUTO && path != WOLFF_PATH_SINGLE && path != WOLFF_PATH_TEAM)
         return fail(WOLFF_EINVAL, "unknown path");
     if (workgroups < 0 || workgroups > 65536) return fail(WOLFF_EINVAL, "bad workgroup count");
-    if (s->q && path == WOLFF_PATH_TEAM) return fail(WOLFF_EINVAL, "Potts lattices run on one workgroup");
     s->path = path;
     s->team_wgs = workgroups;
     return WOLFF_OK;

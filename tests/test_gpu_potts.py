@@ -108,20 +108,47 @@ def test_potts_update_only_and_ordered_start():
 
 
 def test_potts_set_spins_and_paths():
+    # colours set from the host; the one-workgroup and the team path take
+    # turns on the same lattice (each claims with its own mechanism)
     dim, L, q, T, seed = 2, 16, 4, 0.9, 51
     rng = np.random.default_rng(3)
     C = rng.integers(0, q, size=L * L).astype(np.int8)
-    ref, Cref = oracle_potts(dim, L, q, 1.0, T, seed, 100, C.copy())
+    ref, Cref = oracle_potts(dim, L, q, 1.0, T, seed, 120, C.copy())
     with binding.Simulation(dim, L, 1.0, T, seed, q=q) as sim:
-        with pytest.raises(binding.WolffError):
-            sim.set_path(binding.PATH_TEAM, 8)
         with pytest.raises(binding.WolffError):
             sim.set_spins(np.full(L * L, q, dtype=np.int8), 0)
         sim.set_spins(C, 0)
-        sim.run(100)
-        assert (as_array(sim.observables()) == ref).all()
-        assert (sim.spins() == Cref).all()
         assert sim.info().path == binding.PATH_SINGLE
+        sim.run(40)
+        sim.set_path(binding.PATH_TEAM, 8)
+        sim.run(40)
+        sim.set_path(binding.PATH_SINGLE)
+        sim.set_measure(False)
+        sim.run(20)
+        sim.set_measure(True)
+        sim.set_path(binding.PATH_TEAM, 8)
+        sim.run(20)
+        got = as_array(sim.observables())
+        assert (sim.spins() == Cref).all()
+    assert (got[:80] == ref[:80]).all()
+    assert (got[80:100, 0] == binding.NOT_MEASURED).all() and (got[80:100, 1:] == ref[80:100, 1:]).all()
+    assert (got[100:] == ref[100:]).all()
+
+
+@pytest.mark.parametrize("dim,L,q,T,seed,n", [(2, 64, 3, tc_potts_2d(3), 71, 120),
+                                              (2, 33, 4, 0.85, 72, 100),
+                                              (3, 16, 3, 1.7, 73, 80),
+                                              (2, 1024, 3, tc_potts_2d(3), 74, 6)])
+def test_potts_team_path_matches_oracle(dim, L, q, T, seed, n):
+    print("case potts team dim=%d L=%d q=%d" % (dim, L, q), flush=True)
+    ref, Cref = oracle_potts(dim, L, q, 1.0, T, seed, n)
+    with binding.Simulation(dim, L, 1.0, T, seed, q=q) as sim:
+        sim.set_path(binding.PATH_TEAM, 16)
+        sim.run(n)
+        got = as_array(sim.observables())
+        C = sim.spins()
+    assert (got == ref).all()
+    assert (C == Cref).all()
 
 
 def test_potts_server_job_alone_and_in_mix():
