@@ -148,11 +148,14 @@ int wolff_set_stream(wolff_sim *s, void *hip_stream);
 /* Growth path: WOLFF_PATH_SINGLE runs every update in one workgroup (LDS
  * frontier queue, one launch for many updates); WOLFF_PATH_TEAM runs each
  * update on `workgroups` cooperating workgroups (0 = library default) that
- * share an atomic-counter frontier.  WOLFF_PATH_AUTO takes the single path
- * for lattices under 2^20 sites, and for larger ones in "update only" mode
- * while the records last returned by wolff_observables had a mean cluster
- * size under 16384 sites; otherwise the team path.  Every path gives the
- * same records and spins. */
+ * share an atomic-counter frontier.  WOLFF_PATH_AUTO takes the path with
+ * the lower estimated cost per update, from the cluster sizes of the
+ * records last returned by wolff_observables, the lattice size and the
+ * measurement mode (one workgroup: a fixed rate of added sites plus its
+ * lattice recount; team: a cost growing with the cluster's breadth-first
+ * depth); before any records are returned (and after wolff_set_spins) it
+ * takes the single path for lattices under 2^20 sites, the team path
+ * otherwise.  Every path gives the same records and spins. */
 #define WOLFF_PATH_AUTO   0
 #define WOLFF_PATH_SINGLE 1
 #define WOLFF_PATH_TEAM   2

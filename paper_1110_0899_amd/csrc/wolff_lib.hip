@@ -287,6 +287,7 @@ struct wolff_sim {
     bool tagged = false;                  // S may hold member tags of the one-workgroup path
     int path = WOLFF_PATH_AUTO;
     double csize_mean = -1.0;             // mean |C| of the records last returned (-1: none yet)
+    double team_depth_mean = 0.0;         // mean team_depth_us over the same records
     int team_wgs = 0;
     int single_wg = 256;
     int single_q = 2048;
@@ -302,19 +303,46 @@ struct wolff_sim {
     uint64_t grow_n = 0, meas_n = 0;
 };
 
-// Mean cluster size below which a large lattice runs "update only" updates
-// on one workgroup: a few thousand sites are a handful of growth steps, and
-// one launch for many updates beats three launches (seed, team, recount)
-// per update.  With measurement the team path stays: there the one
-// workgroup's periodic lattice recount would cost more than the launches.
-static constexpr double SMALL_CLUSTER = 16384.0;
+// WOLFF_PATH_AUTO compares the cost per update of the two growth paths,
+// estimated from the cluster sizes of the records last returned.  The
+// constants are fits to MI355X timings at and near the critical points
+// (square lattices L = 1024 ... 4096, simple-cubic L = 64 ... 256, Ising and
+// q = 3 Potts, mean clusters from 3 to 2.4e6 sites; both paths within about
+// 20 % of the fit).  One workgroup adds sites at a steady rate and pays for
+// its lattice recount: every 32 measured updates with the incremental bond
+// sum (Ising, even L), every measured update otherwise.  The team's cost is
+// set by the cluster's breadth-first depth (each level is a device-wide
+// round trip), which grows as a power of the cluster size; it is averaged
+// per record because cluster sizes near T_c spread over decades.
+static double team_depth_us(int dim, double c)
+{
+    c = std::max(c, 1.0);
+    return dim == 2 ? 4.2 * std::pow(c, 0.555) : 10.2 * std::pow(c, 0.4);
+}
+
+static double single_cost_us(const wolff_sim* s)
+{
+    const double rate = s->dim == 2 ? 90.0 : 75.0;          // sites per microsecond
+    double recount = 0.0;
+    if (s->measure) {
+        const bool incremental = !s->q && s->L % 2 == 0;
+        recount = incremental ? (double)s->N / (32.0 * 5000.0)
+                              : (double)s->N / (s->dim == 2 ? 11000.0 : 6000.0);
+    }
+    return 13.0 + s->csize_mean / rate + recount;
+}
+
+static double team_cost_us(const wolff_sim* s)
+{
+    return 15.0 + s->team_depth_mean + (s->measure ? 8.0 + (double)s->N / 1e6 : 0.0);
+}
 
 static int resolved_path(const wolff_sim* s)
 {
     if (s->path != WOLFF_PATH_AUTO) return s->path;
-    if (s->N < (1ull << 20)) return WOLFF_PATH_SINGLE;
-    return (!s->measure && s->csize_mean >= 0.0 && s->csize_mean < SMALL_CLUSTER)
-               ? WOLFF_PATH_SINGLE : WOLFF_PATH_TEAM;
+    if (s->csize_mean < 0.0)      // no records yet: by lattice size
+        return s->N < (1ull << 20) ? WOLFF_PATH_SINGLE : WOLFF_PATH_TEAM;
+    return single_cost_us(s) <= team_cost_us(s) ? WOLFF_PATH_SINGLE : WOLFF_PATH_TEAM;
 }
 
 static int team_size(const wolff_sim* s)
@@ -704,9 +732,13 @@ extern "C" int wolff_observables(wolff_sim* s, wolff_record* out, uint64_t cap, 
     if (k) {
         HIP_TRY(hipMemcpy(out, s->d_rec + s->rec_read, k * sizeof(wolff_record),
                           hipMemcpyDeviceToHost));
-        double sum = 0.0;
-        for (uint64_t i = 0; i < k; ++i) sum += (double)out[i].csize;
+        double sum = 0.0, depth = 0.0;
+        for (uint64_t i = 0; i < k; ++i) {
+            sum += (double)out[i].csize;
+            depth += team_depth_us(s->dim, (double)out[i].csize);
+        }
         s->csize_mean = sum / (double)k;      // steers WOLFF_PATH_AUTO
+        s->team_depth_mean = depth / (double)k;
     }
     s->rec_read += k;
     if (n_out) *n_out = k;

@@ -301,30 +301,56 @@ def test_long_measured_run_single(dim, L, T):
     assert (S == Sref).all()
 
 
-def test_auto_path_follows_cluster_size():
-    # a large lattice above T_c, "update only": the first run uses the team
-    # path; once the returned records show small clusters, AUTO moves to one
-    # workgroup, and back to the team path when measurement is switched on;
-    # the records stay on the oracle's trajectory throughout
-    dim, L, T, seed = 2, 1024, 3.2, 29
-    ref, Sref = oracle_series(dim, L, T, seed, 90)
-    with binding.Simulation(dim, L, 1.0, T, seed) as sim:
-        sim.set_measure(False)
+def test_auto_path_follows_cost():
+    # AUTO starts a large lattice on the team path; it then weighs the paths'
+    # costs from the returned cluster sizes.  Small clusters of a measured
+    # Potts lattice stay on the team path (one workgroup would recount the
+    # lattice after each update); "update only" they move to one workgroup,
+    # and back when measurement returns.  The records stay on the oracle's
+    # trajectory throughout.
+    dim, L, q, T, seed, n = 2, 1024, 3, 2.0, 29, 30
+    thr = oracle.potts_threshold(1.0, T)
+    C = oracle.potts_init(dim, L, q, seed)
+    ref = oracle.potts_run(dim, L, q, thr, seed, 0, 3 * n, C)
+    with binding.Simulation(dim, L, 1.0, T, seed, q=q) as sim:
         assert sim.info().path == binding.PATH_TEAM
-        sim.run(30)
+        sim.run(n)
         got1 = as_array(sim.observables())
+        assert sim.info().path == binding.PATH_TEAM
+        sim.set_measure(False)
         assert sim.info().path == binding.PATH_SINGLE
-        sim.run(30)
+        sim.run(n)
         got2 = as_array(sim.observables())
         sim.set_measure(True)
         assert sim.info().path == binding.PATH_TEAM
-        sim.run(30)
+        sim.run(n)
         got3 = as_array(sim.observables())
-        S = sim.spins()
-    got = np.concatenate([got1, got2, got3])
-    assert (got[:60, 1:] == ref[:60, 1:]).all()
-    assert (got[60:] == ref[60:]).all()
-    assert (S == Sref).all()
+        got = np.concatenate([got1, got2, got3])
+        assert (sim.spins() == C).all()
+    assert (got[:n] == ref[:n]).all()
+    assert (got[n:2 * n, 1:] == ref[n:2 * n, 1:]).all()
+    assert (got[2 * n:] == ref[2 * n:]).all()
+
+
+def test_auto_path_picks_one_workgroup_for_mid_size_clusters():
+    # square lattice L = 1024 at T_c with measurement, from the ordered
+    # state: once the clusters have relaxed to a few 1e5 sites (updates
+    # 20 to 40 of this seed), one workgroup is the cheaper path
+    dim, L, T, seed = 2, 1024, TC2, 31
+    thr = oracle.threshold(1.0, T)
+    S = np.ones(L * L, dtype=np.int8)
+    ref = oracle.run(dim, L, thr, seed, 0, 60, S)
+    with binding.Simulation(dim, L, 1.0, T, seed) as sim:
+        sim.set_spins(np.ones(L * L, dtype=np.int8), 0)
+        assert sim.info().path == binding.PATH_TEAM
+        parts = []
+        for _ in range(3):
+            sim.run(20)
+            parts.append(as_array(sim.observables()))
+            if len(parts) == 2:
+                assert sim.info().path == binding.PATH_SINGLE
+        assert (sim.spins() == S).all()
+    assert (np.concatenate(parts) == ref).all()
 
 
 @pytest.mark.parametrize("wg,q", [(64, 64), (128, 128), (256, 2048), (512, 4096), (1024, 1024),
