@@ -514,7 +514,10 @@ def main():
             leg["kernel_frac_of_measured_copy"] = leg["kernel_GBs_algorithmic"] / copy_gbs
 
     achieved = main_leg["grow_GBs_algorithmic"]
-    traffic = counter_traffic("team_kernel", "2d_L4096")
+    team = main_leg["path"] == binding.PATH_TEAM
+    kernel = "team_kernel" if team else "batch_kernel"
+    # the committed counters are the team kernel's at this workload
+    traffic = counter_traffic("team_kernel", "2d_L4096") if team else None
     out = {
         "metric": "added spins/s at Tc, 2D L=4096 & 3D L=256; % HBM peak; batched vs plain",
         "value": main_leg["added_per_s"],
@@ -532,14 +535,15 @@ def main():
             "workload": "2d_L4096_Tc_plain",
             "dim": 2, "L": 4096, "T": workloads.TC_2D, "J": 1.0, "seed": 2,
             "start": "ordered, thermalised for `warmup` updates at T_c",
-            "path": "plain one-lattice launch path (multi-workgroup team kernel)",
+            "path": ("plain one-lattice launch path (multi-workgroup team kernel)" if team
+                     else "plain one-lattice launch path (one-workgroup kernel)"),
             "measurement": "E and M after every update",
             "mean_cluster_size": main_leg["mean_csize"],
             "updates_per_s": main_leg["updates_per_s"],
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "team_kernel (cluster growth)",
+            "kernel": kernel + " (cluster growth)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
