@@ -76,12 +76,15 @@ def ordered_start(n_sites: int) -> np.ndarray:
 
 
 def plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered=True, measure=True,
-              warm_sweeps=0.0, q=0):
+              warm_sweeps=0.0, q=0, path=None):
     """Plain one-lattice path: warmup updates (and, with warm_sweeps, more
     until the flipped spins add up to that many lattice sweeps), then
-    `steps` timed updates."""
+    `steps` timed updates.  path: None for the library's cost-based choice,
+    else a fixed binding.PATH_* value."""
     import torch
     sim = binding.Simulation(dim, L, 1.0, T, seed, q=q)
+    if path is not None:
+        sim.set_path(path)
     sim.set_measure(measure)
     if start_ordered:
         sim.set_spins(np.zeros(L ** dim, dtype=np.int8) if q else ordered_start(L ** dim), 0)
@@ -401,10 +404,11 @@ def profile_only(args, binding, workloads):
         b.copy_(a)
         torch.cuda.synchronize()
         r = {"leg": "copy", "bytes_read": n, "bytes_written": n}
-    elif leg == "plain2d":
-        r = plain_leg(binding, 2, 4096, workloads.TC_2D, 2, args.warmup, args.steps)
-    elif leg == "plain3d":
-        r = plain_leg(binding, 3, 256, workloads.T_3D, 3, args.warmup, args.steps)
+    elif leg in ("plain2d", "plain3d"):
+        path = {"auto": None, "single": binding.PATH_SINGLE, "team": binding.PATH_TEAM}[args.path]
+        dim, L, T, seed = ((2, 4096, workloads.TC_2D, 2) if leg == "plain2d"
+                           else (3, 256, workloads.T_3D, 3))
+        r = plain_leg(binding, dim, L, T, seed, args.warmup, args.steps, path=path)
     elif leg in ("batch2d", "batch3d"):
         wg, q = (int(v) for v in args.tiles.split(","))
         dim, L = (2, 4096) if leg == "batch2d" else (3, 256)
@@ -435,6 +439,8 @@ def main():
     ap.add_argument("--tiles", default="512,2048",
                     help="workgroup size, LDS ring entries of a profiled batch leg (the full "
                          "benchmark takes them from the autotuner)")
+    ap.add_argument("--path", default="auto", choices=("auto", "single", "team"),
+                    help="growth path of a profiled plain leg (default: the library's choice)")
     ap.add_argument("--profile-leg", default=None,
                     help="run only this leg (plain2d, plain3d, batch2d, batch3d, copy) for a "
                          "profiler; prints that leg's numbers instead of the benchmark line")

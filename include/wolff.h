@@ -149,12 +149,12 @@ int wolff_set_stream(wolff_sim *s, void *hip_stream);
  * frontier queue, one launch for many updates); WOLFF_PATH_TEAM runs each
  * update on `workgroups` cooperating workgroups (0 = library default) that
  * share an atomic-counter frontier.  WOLFF_PATH_AUTO takes the path with
- * the lower estimated cost per update, from the cluster sizes of the
- * records last returned by wolff_observables, the lattice size and the
- * measurement mode (one workgroup: a fixed rate of added sites plus its
- * lattice recount; team: a cost growing with the cluster's breadth-first
- * depth); before any records are returned (and after wolff_set_spins) it
- * takes the single path for lattices under 2^20 sites, the team path
+ * the lower estimated cost per update, from the mean cluster size of the
+ * latest records (at most 256) returned by wolff_observables, the lattice
+ * size and the measurement mode (both costs grow with the cluster's
+ * breadth-first depth; one workgroup adds a cost per site and its lattice
+ * recount).  Before any records are returned (and after wolff_set_spins)
+ * it takes the single path for lattices under 2^20 sites, the team path
  * otherwise.  Every path gives the same records and spins. */
 #define WOLFF_PATH_AUTO   0
 #define WOLFF_PATH_SINGLE 1
@@ -162,8 +162,9 @@ int wolff_set_stream(wolff_sim *s, void *hip_stream);
 int wolff_set_path(wolff_sim *s, int path, int workgroups);
 
 /* Workgroup size and LDS frontier ring entries of the one-workgroup path
- * (same ranges as wolff_batch_set_tiles).  Default: 2048 entries and 64
- * threads up to 4096 sites, 128 up to 16384, 256 above. */
+ * (same ranges as wolff_batch_set_tiles).  Default: 64 threads up to 4096
+ * sites, 128 up to 16384, 256 below 2^20 (2048 entries), 512 from 2^20
+ * sites (4096 entries). */
 int wolff_set_tiles(wolff_sim *s, int wg, int queue_entries);
 
 /* Team path: replay a captured HIP graph of `chunk` updates (the seed,

@@ -286,8 +286,7 @@ struct wolff_sim {
     int measure = 1;
     bool tagged = false;                  // S may hold member tags of the one-workgroup path
     int path = WOLFF_PATH_AUTO;
-    double csize_mean = -1.0;             // mean |C| of the records last returned (-1: none yet)
-    double team_depth_mean = 0.0;         // mean team_depth_us over the same records
+    double csize_mean = -1.0;             // mean |C| of the latest records returned (-1: none yet)
     int team_wgs = 0;
     int single_wg = 256;
     int single_q = 2048;
@@ -304,17 +303,17 @@ struct wolff_sim {
 };
 
 // WOLFF_PATH_AUTO compares the cost per update of the two growth paths,
-// estimated from the cluster sizes of the records last returned.  The
-// constants are fits to MI355X timings at and near the critical points
-// (square lattices L = 1024 ... 4096, simple-cubic L = 64 ... 256, Ising and
-// q = 3 Potts, mean clusters from 3 to 2.4e6 sites; both paths within about
-// 20 % of the fit).  One workgroup adds sites at a steady rate and pays for
-// its lattice recount: every 32 measured updates with the incremental bond
-// sum (Ising, even L), every measured update otherwise.  The team's cost is
-// set by the cluster's breadth-first depth (each level is a device-wide
-// round trip), which grows as a power of the cluster size; it is averaged
-// per record because cluster sizes near T_c spread over decades.
-static double team_depth_us(int dim, double c)
+// estimated from the mean cluster size c of the latest records returned.
+// Both are latency-bound by the cluster's breadth-first depth (one step, or
+// one device-wide round trip, per level), modelled as a power of c: on the
+// team path it is the whole cost; one workgroup takes about half as long
+// per level but also adds only ~250 sites per microsecond, and pays for its
+// lattice recount (every 32 measured updates with the incremental bond sum,
+// Ising on even L; every measured update otherwise).  The constants are
+// fits to MI355X timings of both paths at the critical points (square
+// lattices L = 512 ... 4096, simple-cubic L = 64 ... 256, mean clusters
+// from 4e3 to 2.6e6 sites; within about 10 % of the fit, 20 % at 3D L = 64).
+static double depth_us(int dim, double c)
 {
     c = std::max(c, 1.0);
     return dim == 2 ? 4.2 * std::pow(c, 0.555) : 10.2 * std::pow(c, 0.4);
@@ -322,19 +321,18 @@ static double team_depth_us(int dim, double c)
 
 static double single_cost_us(const wolff_sim* s)
 {
-    const double rate = s->dim == 2 ? 90.0 : 75.0;          // sites per microsecond
     double recount = 0.0;
     if (s->measure) {
         const bool incremental = !s->q && s->L % 2 == 0;
         recount = incremental ? (double)s->N / (32.0 * 5000.0)
                               : (double)s->N / (s->dim == 2 ? 11000.0 : 6000.0);
     }
-    return 13.0 + s->csize_mean / rate + recount;
+    return 13.0 + 0.5 * depth_us(s->dim, s->csize_mean) + s->csize_mean / 250.0 + recount;
 }
 
 static double team_cost_us(const wolff_sim* s)
 {
-    return 15.0 + s->team_depth_mean + (s->measure ? 8.0 + (double)s->N / 1e6 : 0.0);
+    return 15.0 + depth_us(s->dim, s->csize_mean) + (s->measure ? 8.0 + (double)s->N / 1e6 : 0.0);
 }
 
 static int resolved_path(const wolff_sim* s)
@@ -447,9 +445,13 @@ static int create_sim(int dim, int L, int q, double J, double T, uint64_t seed, 
     s->seed = seed;
     s->thr = bond_threshold(J, T, q);
     // one-workgroup path: small lattices have frontiers of a few sites per
-    // step, where fewer waves per barrier shorten the step (measured on
-    // MI355X: 64 threads best up to 4096 sites, 128 up to 16384, then 256)
-    s->single_wg = N <= 4096 ? 64 : N <= 16384 ? 128 : 256;
+    // step, where fewer waves per barrier shorten the step; from 2^20 sites
+    // the frontiers of critical clusters fill 512 threads (measured on
+    // MI355X: 64 threads best up to 4096 sites, 128 up to 16384, 256 below
+    // 2^20, then 512 with a 4096-entry ring: -6 % per update at 2D L = 1024,
+    // -35 % at L = 4096, -24 % at 3D L = 256)
+    s->single_wg = N <= 4096 ? 64 : N <= 16384 ? 128 : N < (1ull << 20) ? 256 : 512;
+    s->single_q = N < (1ull << 20) ? 2048 : 4096;
     s->geo = make_geo(dim, (uint32_t)L);
 
 #define CREATE_TRY(expr)                                                                \
@@ -732,13 +734,13 @@ extern "C" int wolff_observables(wolff_sim* s, wolff_record* out, uint64_t cap, 
     if (k) {
         HIP_TRY(hipMemcpy(out, s->d_rec + s->rec_read, k * sizeof(wolff_record),
                           hipMemcpyDeviceToHost));
-        double sum = 0.0, depth = 0.0;
-        for (uint64_t i = 0; i < k; ++i) {
-            sum += (double)out[i].csize;
-            depth += team_depth_us(s->dim, (double)out[i].csize);
-        }
-        s->csize_mean = sum / (double)k;      // steers WOLFF_PATH_AUTO
-        s->team_depth_mean = depth / (double)k;
+        // the latest records (at most 256) steer WOLFF_PATH_AUTO: a long
+        // thermalisation series from an ordered start would otherwise carry
+        // its first, lattice-sized clusters into the estimate
+        const uint64_t from = k > 256 ? k - 256 : 0;
+        double sum = 0.0;
+        for (uint64_t i = from; i < k; ++i) sum += (double)out[i].csize;
+        s->csize_mean = sum / (double)(k - from);
     }
     s->rec_read += k;
     if (n_out) *n_out = k;

@@ -51,6 +51,32 @@ def test_plain_full_size_sampled(dim, L, T, seed):
 
 
 @pytest.mark.parametrize("dim,L,T,seed", SIZES)
+def test_one_workgroup_full_size_sampled(dim, L, T, seed):
+    # the one-workgroup path at its default tiles for these sizes (512
+    # threads, 4096-entry ring), which the cost-based path choice takes for
+    # the simple-cubic lattice at T_c
+    print("case full-size one-workgroup dim=%d L=%d" % (dim, L), flush=True)
+    thr = oracle.threshold(1.0, T)
+    N = L ** dim
+    with binding.Simulation(dim, L, 1.0, T, seed) as sim:
+        sim.set_path(binding.PATH_SINGLE)
+        sim.run(8)
+        got = as_array(sim.observables())
+        S = oracle.init_spins(dim, L, seed)
+        ref = oracle.run(dim, L, thr, seed, 0, 8, S)
+        assert (got == ref).all()
+        assert (sim.spins() == S).all()
+        sim.set_spins(np.ones(N, dtype=np.int8), 700)
+        sim.run(2)
+        got = as_array(sim.observables())
+        S = np.ones(N, dtype=np.int8)
+        ref = oracle.run(dim, L, thr, seed, 700, 2, S)
+        assert (got == ref).all()
+        assert ref[:, 2].max() > N // 4
+        assert (sim.spins() == S).all()
+
+
+@pytest.mark.parametrize("dim,L,T,seed", SIZES)
 def test_batched_full_size_sampled(dim, L, T, seed):
     print("case full-size batch dim=%d L=%d" % (dim, L), flush=True)
     jobs = workloads.same_shape_jobs(dim, L, 2, 2)
