@@ -307,7 +307,8 @@ struct wolff_sim {
 // Both are latency-bound by the cluster's breadth-first depth (one step, or
 // one device-wide round trip, per level), modelled as a power of c: on the
 // team path it is the whole cost; one workgroup takes about half as long
-// per level but also adds only ~250 sites per microsecond, and pays for its
+// per level but also adds only ~250 (2D) or ~200 (3D) sites per
+// microsecond, and pays for its
 // lattice recount (every 32 measured updates with the incremental bond sum,
 // Ising on even L; every measured update otherwise).  The constants are
 // fits to MI355X timings of both paths at the critical points (square
@@ -316,7 +317,7 @@ struct wolff_sim {
 static double depth_us(int dim, double c)
 {
     c = std::max(c, 1.0);
-    return dim == 2 ? 4.2 * std::pow(c, 0.555) : 10.2 * std::pow(c, 0.4);
+    return dim == 2 ? 4.2 * std::pow(c, 0.555) : 9.4 * std::pow(c, 0.4);
 }
 
 static double single_cost_us(const wolff_sim* s)
@@ -327,7 +328,8 @@ static double single_cost_us(const wolff_sim* s)
         recount = incremental ? (double)s->N / (32.0 * 5000.0)
                               : (double)s->N / (s->dim == 2 ? 11000.0 : 6000.0);
     }
-    return 13.0 + 0.5 * depth_us(s->dim, s->csize_mean) + s->csize_mean / 250.0 + recount;
+    const double rate = s->dim == 2 ? 250.0 : 200.0;       // sites per microsecond
+    return 13.0 + 0.5 * depth_us(s->dim, s->csize_mean) + s->csize_mean / rate + recount;
 }
 
 static double team_cost_us(const wolff_sim* s)
