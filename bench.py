@@ -113,6 +113,7 @@ def plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered=True, measu
     log("%dD L=%d: %d warmup updates in %.1f s" % (dim, L, warmup, time.time() - t0))
     checkpoint = sim.spins()
     t_ckpt = sim.info().t
+    path_timed = int(sim.info().path)        # the path the timed updates take
     sim.profile(True)
     torch.cuda.synchronize()
     sim.synchronize()
@@ -138,7 +139,7 @@ def plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered=True, measu
         "updates_per_s": steps / wall, "mean_csize": added / max(steps, 1),
         "grow_ms": grow_ms, "grow_launches": prof["grow_launches"],
         "measure_ms": prof["measure_ms"], "measure_launches": prof["measure_launches"],
-        "grow_GBs_algorithmic": achieved, "path": int(info.path),
+        "grow_GBs_algorithmic": achieved, "path": path_timed, "path_after": int(info.path),
         "records": rec, "checkpoint": checkpoint, "t_ckpt": t_ckpt,
     }
 
