@@ -276,7 +276,7 @@ def sweep_point(binding, dim, L, T, seed, warmup, steps, start_ordered, cpu_seco
             "gpu_ms_update_only": 1e3 * u["wall_s"] / steps, "gpu_ms_measure": gpu_ms,
             "cpu_ms_measure": cpu_ms, "cpu_updates": cpu["updates"],
             "cpu_records_match": cpu["records_match_gpu"], "speedup_measure": cpu_ms / gpu_ms,
-            "path": m["path"]}
+            "path": m["path"], "path_update_only": u["path"]}
 
 
 def sizes_leg(binding, workloads, cpu_seconds):
