@@ -635,7 +635,12 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
             __syncthreads();
             if (incr && active && par != 0u) SG[self] = xb;           // every read of the step is done
             // the step's claims are settled: empty the table for the next step
-            for (uint32_t i = tid; i < tab_entries(WG); i += WG) tab[i] = TAB_EMPTY;
+            {   // eight entries per thread: two 16-byte stores
+                uint4* t4 = reinterpret_cast<uint4*>(tab) + 2u * tid;
+                const uint4 e = make_uint4(TAB_EMPTY, TAB_EMPTY, TAB_EMPTY, TAB_EMPTY);
+                t4[0] = e;
+                t4[1] = e;
+            }
             uint32_t before = 0u, total = 0u;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
@@ -716,7 +721,7 @@ __global__ __launch_bounds__(WG) void batch_kernel(Rep* reps, const uint32_t* or
                                                    uint32_t max_updates, uint32_t qmask,
                                                    uint64_t budget)
 {
-    extern __shared__ uint32_t q[];
+    extern __shared__ __align__(16) uint32_t q[];
     __shared__ uint32_t wave_cnt[WG / WAVE];
     __shared__ long long red[2 * (WG / WAVE)];
     __shared__ WgCtl ctl;
@@ -848,7 +853,7 @@ __global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned
                                                   uint32_t qmask, uint32_t keep)
 {
     constexpr int NW = WG / WAVE;
-    extern __shared__ uint32_t q[];
+    extern __shared__ __align__(16) uint32_t q[];
     __shared__ uint32_t wave_cnt[NW];
     __shared__ uint32_t sh_take[3];   // first slot, count, done flag
     __shared__ uint32_t sh_push;
