@@ -7,7 +7,7 @@ identical and the results bit-equal), and the candidate with the shortest
 kernel time wins.  Results are cached in a JSON file keyed by
 (GPU architecture, dim, log2 of L rounded up, replica count class); the file
 is $WOLFF_TUNE_CACHE or ~/.cache/wolff_mi355x_tune.json (Potts replica sets
-have keys of their own).
+have keys of their own, and so does each mixed set of shapes).
 """
 from __future__ import annotations
 
@@ -76,11 +76,25 @@ def measure(jobs, wg: int, q: int, warm: int, timed: int, start: int) -> float:
         return b.last_ms()
 
 
+def set_key(jobs) -> str:
+    """Cache key of a job list: the class of its jobs when they share one;
+    else the class of its largest shape marked as mixed, with a digest of
+    every job's (dim, L, q), so that a mixed set never reads a same-class
+    entry.  The key does not depend on the order of the jobs."""
+    shapes = sorted((j.dim, j.L, getattr(j, "q", 0)) for j in jobs)
+    classes = {key(d, L, len(jobs), q) for d, L, q in shapes}
+    d, L, q = shapes[-1]
+    k = key(d, L, len(jobs), q)
+    if len(classes) > 1:
+        import hashlib
+        k += "|mixed:" + hashlib.sha256(repr(shapes).encode()).hexdigest()[:12]
+    return k
+
+
 def tune(jobs, warm: int = 4, timed: int = 4, start: int = 1, candidates=None,
          use_cache: bool = True, log=None) -> dict:
-    """Best (wg, queue_entries) for a list of same-class jobs."""
-    j0 = jobs[0]
-    k = key(j0.dim, j0.L, len(jobs), getattr(j0, "q", 0))
+    """Best (wg, queue_entries) for a list of jobs (cached per set_key)."""
+    k = set_key(jobs)
     if use_cache:
         hit = _load_cache().get(k)
         if hit:

@@ -68,6 +68,21 @@ def test_tuner_keys_and_cache(tmp_path, monkeypatch):
     assert all(wg <= 1024 and q >= wg and q & (q - 1) == 0 for wg, q in autotune.CANDIDATES)
 
 
+def test_tuner_key_of_mixed_sets():
+    # a same-class set keys by its class; a mixed set (C4) never shares that
+    # key, and its key follows the multiset of shapes, not the job order
+    same = workloads.same_shape_jobs(2, 512, 320, 8)
+    assert autotune.set_key(same) == autotune.key(2, 512, 320)
+    mixed = workloads.c4_jobs(8)
+    k = autotune.set_key(mixed)
+    assert k.startswith(autotune.key(3, 128, len(mixed)) + "|mixed:")   # largest shape: 3D L=128
+    assert autotune.set_key(list(reversed(mixed))) == k
+    assert autotune.set_key(mixed[:-1]) != k
+    # classes round L up to powers of two: L = 200 and 256 share one
+    a = [workloads.Job(3, 200, 4.5, 1, 8), workloads.Job(3, 256, 4.5, 2, 8)]
+    assert autotune.set_key(a) == autotune.key(3, 256, 2)
+
+
 def test_serving_percentiles():
     xs = list(range(1, 101))
     assert serve.percentile(xs, 50) == pytest.approx(50.5)
