@@ -327,6 +327,37 @@ def potts_leg(binding, workloads, args):
             "batch_2d_L4096": b}
 
 
+def handoff_leg(reps=2000):
+    """The fixed cost a host-started update would pay on this machine (the
+    paper's hybrid start, Table 3): a synchronised device-to-host and
+    host-to-device copy of a small frontier in pinned memory, and one kernel
+    launch with a host synchronisation.  Plumbing only: no growth runs."""
+    import torch
+    dev = torch.device("cuda:0")
+    out = {"round_trip_us": {}}
+    for nbytes in (512, 4096, 65536):
+        d = torch.zeros(nbytes // 4, dtype=torch.int32, device=dev)
+        h = torch.zeros(nbytes // 4, dtype=torch.int32).pin_memory()
+        for it in range(200 + reps):
+            if it == 200:
+                a = time.perf_counter()
+            h.copy_(d, non_blocking=True)
+            torch.cuda.synchronize()
+            d.copy_(h, non_blocking=True)
+            torch.cuda.synchronize()
+        out["round_trip_us"][str(nbytes)] = (time.perf_counter() - a) / reps * 1e6
+    x = torch.zeros(1, device=dev)
+    for it in range(200 + reps):
+        if it == 200:
+            a = time.perf_counter()
+        x.add_(1.0)
+        torch.cuda.synchronize()
+    out["launch_sync_us"] = (time.perf_counter() - a) / reps * 1e6
+    log("hand-off: round trip %s us, launch + sync %.1f us"
+        % (", ".join("%s B %.1f" % kv for kv in out["round_trip_us"].items()), out["launch_sync_us"]))
+    return out
+
+
 def copy_peak_gbs(reps=5):
     """Device-to-device copy bandwidth (read + write bytes / time), 2 GiB."""
     import torch
@@ -439,8 +470,8 @@ def main():
     ap.add_argument("--batch-warmup", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--sweep-cpu-seconds", type=float, default=4.0,
-                    help="oracle time per point of the sweeps (legs sizes, temps, potts; run "
-                         "without plain2d, they print their own JSON line)")
+                    help="oracle time per point of the sweeps (legs sizes, temps, potts, handoff; "
+                         "run without plain2d, they print their own JSON line)")
     ap.add_argument("--tiles", default="512,2048",
                     help="workgroup size, LDS ring entries of a profiled batch leg (the full "
                          "benchmark takes them from the autotuner)")
@@ -477,6 +508,8 @@ def main():
             out["temps"] = temps_leg(binding, workloads, args.sweep_cpu_seconds)
         if "potts" in legs:
             out["potts"] = potts_leg(binding, workloads, args)
+        if "handoff" in legs:
+            out["handoff"] = handoff_leg()
         print(json.dumps(out), flush=True)
         return
 
