@@ -482,7 +482,7 @@ def main():
                          "profiler; prints that leg's numbers instead of the benchmark line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(independent lattices would shard across GPUs with no exchange).", file=sys.stderr)
         sys.exit(2)
 

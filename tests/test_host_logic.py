@@ -3,6 +3,9 @@ autotuner's cache, the serving statistics and the Potts critical
 temperature used by the benchmarks."""
 import json
 import math
+import os
+import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -88,3 +91,12 @@ def test_serving_percentiles():
     assert serve.percentile(xs, 50) == pytest.approx(50.5)
     assert serve.percentile(xs, 99) == pytest.approx(99.01)
     assert math.isnan(serve.percentile([], 50))
+
+
+def test_bench_refuses_several_gpus():
+    # one GPU only: --gpus above 1 exits with a message before touching a device
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=root, capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
