@@ -457,7 +457,7 @@ def profile_only(args, binding, workloads):
     print(json.dumps(r), flush=True)
 
 
-def main():
+def build_parser() -> argparse.ArgumentParser:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000, help="timed updates of the headline leg")
@@ -478,8 +478,14 @@ def main():
     ap.add_argument("--path", default="auto", choices=("auto", "single", "team"),
                     help="growth path of a profiled plain leg (default: the library's choice)")
     ap.add_argument("--profile-leg", default=None,
+                    choices=("plain2d", "plain3d", "batch2d", "batch3d", "copy"),
                     help="run only this leg (plain2d, plain3d, batch2d, batch3d, copy) for a "
                          "profiler; prints that leg's numbers instead of the benchmark line")
+    return ap
+
+
+def main():
+    ap = build_parser()
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
