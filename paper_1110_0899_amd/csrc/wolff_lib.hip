@@ -308,12 +308,12 @@ struct wolff_sim {
 // one device-wide round trip, per level), modelled as a power of c: on the
 // team path it is the whole cost; one workgroup takes about half as long
 // per level but also adds only ~250 (2D) or ~200 (3D) sites per
-// microsecond, and pays for its
-// lattice recount (every 32 measured updates with the incremental bond sum,
-// Ising on even L; every measured update otherwise).  The constants are
-// fits to MI355X timings of both paths at the critical points (square
-// lattices L = 512 ... 4096, simple-cubic L = 64 ... 256, mean clusters
-// from 4e3 to 2.6e6 sites; within about 10 % of the fit, 20 % at 3D L = 64).
+// microsecond, and pays for its lattice recount (every 32 measured updates
+// with the incremental bond sum, Ising on even L; every measured update
+// otherwise).  The constants are fits to MI355X timings of both paths, at
+// their default tiles, at the critical points (square lattices
+// L = 512 ... 4096, simple-cubic L = 64 ... 256, mean clusters from 4e3 to
+// 2.6e6 sites; within about 10 % of the fit, 20 % at 3D L = 64).
 static double depth_us(int dim, double c)
 {
     c = std::max(c, 1.0);
