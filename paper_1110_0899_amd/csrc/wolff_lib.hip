@@ -37,6 +37,19 @@ static int fail(int code, const std::string& msg)
         }                                                                               \
     } while (0)
 
+// Every fill and copy of a handle's device memory is ordered on the handle's
+// stream.  The library's own streams are non-blocking: they do not wait for
+// work on the null stream, so a hipMemset / hipMemcpy issued there could
+// land after a kernel that the handle's stream runs later.  Copies that
+// return host data (or read host data) wait for the stream before returning.
+static hipError_t copy_wait(hipStream_t st, void* dst, const void* src, size_t bytes,
+                            hipMemcpyKind kind)
+{
+    const hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
+
 extern "C" const char* wolff_strerror(int code)
 {
     switch (code) {
@@ -131,17 +144,17 @@ static uint64_t host_site_addr(const Geo& g, int dim, uint64_t i)
 // Device spins (storage order) -> host spins (site order), and back.
 // Ising bytes may carry member tags; bit 1 is the sign of every byte.
 // Potts bytes (q > 0) are the colours.
-static int copy_spins_out(const Geo& g, int dim, const int8_t* dev, int8_t* host, uint64_t n,
-                          int q = 0)
+static int copy_spins_out(hipStream_t st, const Geo& g, int dim, const int8_t* dev, int8_t* host,
+                          uint64_t n, int q = 0)
 {
     if (!g.tiled) {
-        HIP_TRY(hipMemcpy(host, dev, n, hipMemcpyDeviceToHost));
+        HIP_TRY(copy_wait(st, host, dev, n, hipMemcpyDeviceToHost));
         if (!q)
             for (uint64_t i = 0; i < n; ++i) host[i] = (host[i] & 2) ? -1 : 1;
         return WOLFF_OK;
     }
     std::vector<int8_t> tmp(n);
-    HIP_TRY(hipMemcpy(tmp.data(), dev, n, hipMemcpyDeviceToHost));
+    HIP_TRY(copy_wait(st, tmp.data(), dev, n, hipMemcpyDeviceToHost));
     for (uint64_t i = 0; i < n; ++i) {
         const int8_t b = tmp[host_site_addr(g, dim, i)];
         host[i] = q ? b : ((b & 2) ? -1 : 1);
@@ -149,15 +162,16 @@ static int copy_spins_out(const Geo& g, int dim, const int8_t* dev, int8_t* host
     return WOLFF_OK;
 }
 
-static int copy_spins_in(const Geo& g, int dim, const int8_t* host, int8_t* dev, uint64_t n)
+static int copy_spins_in(hipStream_t st, const Geo& g, int dim, const int8_t* host, int8_t* dev,
+                         uint64_t n)
 {
     if (!g.tiled) {
-        HIP_TRY(hipMemcpy(dev, host, n, hipMemcpyHostToDevice));
+        HIP_TRY(copy_wait(st, dev, host, n, hipMemcpyHostToDevice));
         return WOLFF_OK;
     }
     std::vector<int8_t> tmp(n);
     for (uint64_t i = 0; i < n; ++i) tmp[host_site_addr(g, dim, i)] = host[i];
-    HIP_TRY(hipMemcpy(dev, tmp.data(), n, hipMemcpyHostToDevice));
+    HIP_TRY(copy_wait(st, dev, tmp.data(), n, hipMemcpyHostToDevice));
     return WOLFF_OK;
 }
 
@@ -410,14 +424,13 @@ static int harvest_events(wolff_sim* s)
 // Copy the host-side fields of the descriptor (stream must be idle).
 static int push_rep(wolff_sim* s, const Rep& r)
 {
-    HIP_TRY(hipMemcpy(s->d_rep, &r, sizeof(Rep), hipMemcpyHostToDevice));
+    HIP_TRY(copy_wait(s->stream, s->d_rep, &r, sizeof(Rep), hipMemcpyHostToDevice));
     return WOLFF_OK;
 }
 
 static int pull_rep(wolff_sim* s, Rep* r)
 {
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    HIP_TRY(hipMemcpy(r, s->d_rep, sizeof(Rep), hipMemcpyDeviceToHost));
+    HIP_TRY(copy_wait(s->stream, r, s->d_rep, sizeof(Rep), hipMemcpyDeviceToHost));
     return WOLFF_OK;
 }
 
@@ -469,14 +482,14 @@ static int create_sim(int dim, int L, int q, double J, double T, uint64_t seed, 
     CREATE_TRY(hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking));
     s->stream = s->own_stream;
     CREATE_TRY(hipMalloc(&s->S, padded_bytes(N)));
-    CREATE_TRY(hipMemset(s->S, 0, padded_bytes(N)));
+    CREATE_TRY(hipMemsetAsync(s->S, 0, padded_bytes(N), s->stream));
     CREATE_TRY(hipMalloc(&s->ov, N * sizeof(uint32_t)));
     CREATE_TRY(hipMalloc(&s->d_rep, sizeof(Rep)));
     CREATE_TRY(hipMalloc(&s->d_order, sizeof(uint32_t)));
     CREATE_TRY(hipMalloc(&s->d_next, sizeof(uint32_t)));
     CREATE_TRY(hipMalloc(&s->d_ctl, sizeof(TeamCtl)));
-    CREATE_TRY(hipMemset(s->d_ctl, 0, sizeof(TeamCtl)));
-    CREATE_TRY(hipMemset(s->d_order, 0, sizeof(uint32_t)));
+    CREATE_TRY(hipMemsetAsync(s->d_ctl, 0, sizeof(TeamCtl), s->stream));
+    CREATE_TRY(hipMemsetAsync(s->d_order, 0, sizeof(uint32_t), s->stream));
     s->rec_cap = 1024;
     CREATE_TRY(hipMalloc(&s->d_rec, s->rec_cap * sizeof(wolff_record)));
 
@@ -500,8 +513,7 @@ static int create_sim(int dim, int L, int q, double J, double T, uint64_t seed, 
     r.n_left = 0xFFFFFFFFu;
     r.measure = 1;
     r.err = 0;
-    CREATE_TRY(hipStreamSynchronize(s->stream));
-    CREATE_TRY(hipMemcpy(s->d_rep, &r, sizeof(Rep), hipMemcpyHostToDevice));
+    CREATE_TRY(copy_wait(s->stream, s->d_rep, &r, sizeof(Rep), hipMemcpyHostToDevice));
     if ((rc = measure_now(s)) != WOLFF_OK) {
         free_sim(s);
         return rc;
@@ -541,7 +553,7 @@ static int reserve_records(wolff_sim* s, uint64_t n)
     HIP_TRY(hipMalloc(&nrec, cap * sizeof(wolff_record)));
     const uint64_t live = s->rec_written - s->rec_read;
     if (live)
-        HIP_TRY(hipMemcpy(nrec, s->d_rec + s->rec_read, live * sizeof(wolff_record),
+        HIP_TRY(copy_wait(s->stream, nrec, s->d_rec + s->rec_read, live * sizeof(wolff_record),
                           hipMemcpyDeviceToDevice));
     HIP_TRY(hipFree(s->d_rec));
     s->d_rec = nrec;
@@ -561,7 +573,7 @@ static int ensure_team_queue(wolff_sim* s)
     if (s->gq) return WOLFF_OK;
     HIP_TRY(hipStreamSynchronize(s->stream));
     HIP_TRY(hipMalloc(&s->gq, s->N * sizeof(unsigned long long)));
-    HIP_TRY(hipMemset(s->gq, 0, s->N * sizeof(unsigned long long)));
+    HIP_TRY(hipMemsetAsync(s->gq, 0, s->N * sizeof(unsigned long long), s->stream));
     return WOLFF_OK;
 }
 
@@ -734,7 +746,7 @@ extern "C" int wolff_observables(wolff_sim* s, wolff_record* out, uint64_t cap, 
     const uint64_t live = s->rec_written - s->rec_read;
     const uint64_t k = std::min(cap, live);
     if (k) {
-        HIP_TRY(hipMemcpy(out, s->d_rec + s->rec_read, k * sizeof(wolff_record),
+        HIP_TRY(copy_wait(s->stream, out, s->d_rec + s->rec_read, k * sizeof(wolff_record),
                           hipMemcpyDeviceToHost));
         // the latest records (at most 256) steer WOLFF_PATH_AUTO: a long
         // thermalisation series from an ordered start would otherwise carry
@@ -790,8 +802,7 @@ extern "C" int wolff_get_spins(wolff_sim* s, int8_t* host, uint64_t n)
 {
     if (!s || !host) return fail(WOLFF_EINVAL, "NULL argument");
     if (n != s->N) return fail(WOLFF_EINVAL, "n must equal the number of sites");
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    return copy_spins_out(s->geo, s->dim, s->S, host, n, s->q);
+    return copy_spins_out(s->stream, s->geo, s->dim, s->S, host, n, s->q);
 }
 
 extern "C" int wolff_set_spins(wolff_sim* s, const int8_t* host, uint64_t n, uint64_t t)
@@ -809,7 +820,7 @@ extern "C" int wolff_set_spins(wolff_sim* s, const int8_t* host, uint64_t n, uin
     Rep r;
     int rc = pull_rep(s, &r);
     if (rc) return rc;
-    if ((rc = copy_spins_in(s->geo, s->dim, host, s->S, n))) return rc;
+    if ((rc = copy_spins_in(s->stream, s->geo, s->dim, host, s->S, n))) return rc;
     r.t = (uint32_t)t;
     r.t_norm = (uint32_t)t;
     r.rec_count = 0;
@@ -968,7 +979,7 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
     BATCH_TRY(hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking));
     b->stream = b->own_stream;
     BATCH_TRY(hipMalloc(&b->S, s_total));
-    BATCH_TRY(hipMemset(b->S, 0, s_total));
+    BATCH_TRY(hipMemsetAsync(b->S, 0, s_total, b->stream));
     BATCH_TRY(hipMalloc(&b->ov, ov_total * sizeof(uint32_t)));
     BATCH_TRY(hipMalloc(&b->rec, rec_total * sizeof(wolff_record)));
     BATCH_TRY(hipMalloc(&b->d_reps, n_jobs * sizeof(Rep)));
@@ -1005,7 +1016,8 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
         b->t.push_back(0);
         b->rec_read.push_back(0);
     }
-    BATCH_TRY(hipMemcpy(b->d_reps, b->reps.data(), n_jobs * sizeof(Rep), hipMemcpyHostToDevice));
+    BATCH_TRY(copy_wait(b->stream, b->d_reps, b->reps.data(), n_jobs * sizeof(Rep),
+                        hipMemcpyHostToDevice));
     for (int i = 0; i < n_jobs; ++i) {
         hipLaunchKernelGGL(wolff::measure_rep_kernel<1024>, dim3(1), dim3(1024), 0, b->stream,
                            b->d_reps + i);
@@ -1019,7 +1031,8 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
         const double wy = (double)Ns[y] * (double)b->reps[y].thr * (double)std::max<uint64_t>(jobs[y].n_updates, 1);
         return wx > wy;
     });
-    BATCH_TRY(hipMemcpy(b->d_order, b->order.data(), n_jobs * sizeof(uint32_t), hipMemcpyHostToDevice));
+    BATCH_TRY(copy_wait(b->stream, b->d_order, b->order.data(), n_jobs * sizeof(uint32_t),
+                        hipMemcpyHostToDevice));
     BATCH_TRY(hipStreamSynchronize(b->stream));
 #undef BATCH_TRY
     *out = b;
@@ -1044,12 +1057,11 @@ extern "C" int wolff_batch_set_tiles(wolff_batch* b, int wg, int queue_entries)
 extern "C" int wolff_batch_set_measure(wolff_batch* b, int on)
 {
     if (!b) return fail(WOLFF_EINVAL, "batch is NULL");
-    HIP_TRY(hipStreamSynchronize(b->stream));
     std::vector<Rep> cur(b->reps.size());
-    HIP_TRY(hipMemcpy(cur.data(), b->d_reps, cur.size() * sizeof(Rep), hipMemcpyDeviceToHost));
+    HIP_TRY(copy_wait(b->stream, cur.data(), b->d_reps, cur.size() * sizeof(Rep), hipMemcpyDeviceToHost));
     b->measure = on ? 1 : 0;
     for (auto& r : cur) r.measure = (uint32_t)b->measure;
-    HIP_TRY(hipMemcpy(b->d_reps, cur.data(), cur.size() * sizeof(Rep), hipMemcpyHostToDevice));
+    HIP_TRY(copy_wait(b->stream, b->d_reps, cur.data(), cur.size() * sizeof(Rep), hipMemcpyHostToDevice));
     return WOLFF_OK;
 }
 
@@ -1140,13 +1152,12 @@ extern "C" int wolff_batch_records(wolff_batch* b, int job, wolff_record* out, u
 {
     if (!b || job < 0 || (size_t)job >= b->jobs.size() || (!out && cap > 0))
         return fail(WOLFF_EINVAL, "bad argument");
-    HIP_TRY(hipStreamSynchronize(b->stream));
     Rep r;
-    HIP_TRY(hipMemcpy(&r, b->d_reps + job, sizeof(Rep), hipMemcpyDeviceToHost));
+    HIP_TRY(copy_wait(b->stream, &r, b->d_reps + job, sizeof(Rep), hipMemcpyDeviceToHost));
     const uint64_t live = r.rec_count - b->rec_read[job];
     const uint64_t k = std::min(cap, live);
     if (k)
-        HIP_TRY(hipMemcpy(out, b->rec + b->rec_off[job] + b->rec_read[job],
+        HIP_TRY(copy_wait(b->stream, out, b->rec + b->rec_off[job] + b->rec_read[job],
                           k * sizeof(wolff_record), hipMemcpyDeviceToHost));
     b->rec_read[job] += k;
     if (n_out) *n_out = k;
@@ -1159,8 +1170,7 @@ extern "C" int wolff_batch_get_spins(wolff_batch* b, int job, int8_t* host, uint
     if (!b || job < 0 || (size_t)job >= b->jobs.size() || !host) return fail(WOLFF_EINVAL, "bad argument");
     const Rep& r = b->reps[job];
     if (n != r.geo.N) return fail(WOLFF_EINVAL, "n must equal the number of sites");
-    HIP_TRY(hipStreamSynchronize(b->stream));
-    return copy_spins_out(r.geo, r.dim, r.S, host, n, (int)r.q);
+    return copy_spins_out(b->stream, r.geo, r.dim, r.S, host, n, (int)r.q);
 }
 
 // ================================================================== server
@@ -1264,7 +1274,8 @@ extern "C" int wolff_server_create(uint64_t hbm_budget_bytes, int max_slots, wol
     {
         std::vector<uint32_t> ident(v->slots);
         for (uint64_t i = 0; i < v->slots; ++i) ident[i] = (uint32_t)i;
-        SRV_TRY(hipMemcpy(v->d_order, ident.data(), v->slots * sizeof(uint32_t), hipMemcpyHostToDevice));
+        SRV_TRY(copy_wait(v->stream, v->d_order, ident.data(), v->slots * sizeof(uint32_t),
+                          hipMemcpyHostToDevice));
     }
     SRV_TRY(hipEventCreate(&v->ev_a));
     SRV_TRY(hipEventCreate(&v->ev_b));
@@ -1389,8 +1400,8 @@ extern "C" int wolff_server_step(wolff_server* v, double quantum_ms, uint64_t* n
                 const uint64_t cnt = j.rep.rec_count;
                 j.results.resize(cnt);
                 if (cnt)
-                    HIP_TRY(hipMemcpy(j.results.data(), j.rep.rec, cnt * sizeof(wolff_record),
-                                      hipMemcpyDeviceToHost));
+                    HIP_TRY(copy_wait(v->stream, j.results.data(), j.rep.rec,
+                                      cnt * sizeof(wolff_record), hipMemcpyDeviceToHost));
                 for (const auto& r : j.results) v->added += (uint64_t)r.csize;
                 HIP_TRY(hipFreeAsync(j.block, v->stream));
                 j.block = nullptr;

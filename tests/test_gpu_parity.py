@@ -60,6 +60,24 @@ def test_initial_state_matches_oracle():
         assert info.mag == M and info.bond_sum == B
 
 
+@pytest.mark.parametrize("dim,L,seed", [(2, 3, 103), (2, 5, 7), (3, 3, 11), (2, 33, 9)])
+def test_fresh_handle_state_before_any_copy(dim, L, seed):
+    # the observables of a fresh handle are those of the lattice its init
+    # kernel wrote: read them, and one update, before any spin copy (a copy
+    # synchronises the device and could hide a fill that is not ordered on
+    # the handle's stream)
+    T = TC2 if dim == 2 else T3
+    print("case fresh dim=%d L=%d seed=%d" % (dim, L, seed), flush=True)
+    with binding.Simulation(dim, L, 1.0, T, seed) as sim:
+        info = sim.info()
+        sim.run(1)
+        rec = as_array(sim.observables())
+    B, M = oracle.observables(dim, L, oracle.init_spins(dim, L, seed))
+    assert (info.mag, info.bond_sum) == (M, B)
+    ref, _ = oracle_series(dim, L, T, seed, 1)
+    assert (rec == ref).all()
+
+
 def test_c1_full_run_single_path():
     c = workloads.C1
     got, S, info = gpu_series(2, c["L"], c["T"], c["seed"], c["n_meas"], binding.PATH_SINGLE)
