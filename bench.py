@@ -37,6 +37,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_ADDED = {2: 21.0, 3: 23.0}
+# Thermalisation of the headline lattices from the ordered state, whatever
+# --warmup asks for: at least this many updates at T_c before the timed ones
+# (the ordered start relaxes to the critical cluster-size level within a few
+# hundred updates; a random start would take more than 10^6 at L = 4096)
+MIN_THERM = {2: 1000, 3: 3000}
 PAPER_CONTEXT = {
     "2d_L4096": "paper: 5.60x over one Xeon W3520 core (GTX 285, 83.95 ms/update incl. measurement)",
     "3d_L256": "paper: 7.90x over one Xeon W3520 core (GTX 285, 17.45 ms/update incl. measurement)",
@@ -91,7 +96,8 @@ def plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered=True, measu
     t0 = time.time()
     sim.run(warmup)
     sim.synchronize()
-    sim.observables()
+    therm = sim.observables()
+    therm_mean = float(therm["csize"][-200:].mean()) if len(therm) else 0.0
     if warm_sweeps:
         # small clusters: thermalise "update only" until the flipped spins add
         # up to warm_sweeps lattices
@@ -141,6 +147,7 @@ def plain_leg(binding, dim, L, T, seed, warmup, steps, start_ordered=True, measu
         "measure_ms": prof["measure_ms"], "measure_launches": prof["measure_launches"],
         "grow_GBs_algorithmic": achieved, "path": path_timed, "path_after": int(info.path),
         "records": rec, "checkpoint": checkpoint, "t_ckpt": t_ckpt,
+        "therm_mean_csize": therm_mean,
     }
 
 
@@ -376,23 +383,30 @@ def copy_peak_gbs(reps=5):
     return 2.0 * n * reps / el / 1e9
 
 
-def serve_leg(workloads, quantum_ms=5.0, n_jobs=2000, max_wall_s=20.0):
-    """Serving form: capacity from a closed batch of stream jobs, then the
-    Poisson stream at 1.2x that rate through the continuous-batching loop."""
+def serve_leg(binding, workloads, quantum_ms=5.0, n_jobs=2000, max_wall_s=30.0):
+    """Serving form, measurement on: the loop's capacity from a saturated
+    closed batch of stream-shaped jobs (twice its slots, all queued at once),
+    then the Poisson stream at 1.2x that rate through the continuous-batching
+    loop."""
     from paper_1110_0899_amd import serve
-    sample = workloads.c5_stream(n_jobs=200, rate_per_s=1.0, seed=55)
+    with binding.Server() as probe:
+        slots = int(probe.stats()["slots"])
+    sample = workloads.c5_stream(n_jobs=2 * slots + 200, rate_per_s=1.0, seed=55)
     capinfo = serve.capacity(sample, quantum_ms, progress=log)
     cap = capinfo["jobs_per_s"]
     rate = 1.2 * cap
     stream = workloads.c5_stream(n_jobs=n_jobs, rate_per_s=rate)
     r = serve.run_stream(stream, quantum_ms=quantum_ms, max_wall_s=max_wall_s, progress=log)
     r.pop("records", None)
+    r.pop("finish_s", None)
+    last_arrival = max(j.arrival_s for j in stream if j.arrival_s <= max_wall_s)
     r.update({"capacity_jobs_per_s": cap, "capacity_estimate": capinfo,
-              "arrival_rate_jobs_per_s": rate,
-              "quantum_ms": quantum_ms, "records": "update only (bond sum not measured per update)"})
-    log("serve: capacity %.1f jobs/s, stream at %.1f jobs/s: %d jobs, p50 %.3f s, p99 %.3f s, "
-        "%.3e added/s" % (cap, rate, r["jobs"], r["p50_latency_s"], r["p99_latency_s"],
-                          r["added_per_s"]))
+              "arrival_rate_jobs_per_s": rate, "arrival_span_s": last_arrival,
+              "quantum_ms": quantum_ms, "records": "E and M measured after every update"})
+    log("serve: capacity %.1f jobs/s (closed batch of %d), stream at %.1f jobs/s over %.1f s: "
+        "%d jobs, p50 %.3f s, p99 %.3f s, %.3e added/s"
+        % (cap, capinfo["jobs"], rate, last_arrival, r["jobs"], r["p50_latency_s"],
+           r["p99_latency_s"], r["added_per_s"]))
     return r
 
 
@@ -444,7 +458,8 @@ def profile_only(args, binding, workloads):
         path = {"auto": None, "single": binding.PATH_SINGLE, "team": binding.PATH_TEAM}[args.path]
         dim, L, T, seed = ((2, 4096, workloads.TC_2D, 2) if leg == "plain2d"
                            else (3, 256, workloads.T_3D, 3))
-        r = plain_leg(binding, dim, L, T, seed, args.warmup, args.steps, path=path)
+        r = plain_leg(binding, dim, L, T, seed, max(args.warmup, MIN_THERM[dim]), args.steps,
+                      path=path)
     elif leg in ("batch2d", "batch3d"):
         wg, q = (int(v) for v in args.tiles.split(","))
         dim, L = (2, 4096) if leg == "batch2d" else (3, 256)
@@ -519,10 +534,12 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
-    main_leg = plain_leg(binding, 2, 4096, workloads.TC_2D, 2, args.warmup, args.steps)
+    main_leg = plain_leg(binding, 2, 4096, workloads.TC_2D, 2, max(args.warmup, MIN_THERM[2]),
+                         args.steps)
     cpu = cpu_baseline(main_leg, args.cpu_seconds)
     if "plain3d" in legs:
-        l3 = plain_leg(binding, 3, 256, workloads.T_3D, 3, 3 * args.warmup, 5 * args.steps)
+        l3 = plain_leg(binding, 3, 256, workloads.T_3D, 3, max(3 * args.warmup, MIN_THERM[3]),
+                       5 * args.steps)
         extra["plain_3d_L256"] = {k: v for k, v in l3.items()
                                   if k not in ("records", "checkpoint")}
     if "batch2d" in legs:
@@ -542,13 +559,13 @@ def main():
 
     if "updateonly" in legs:
         # the paper's Table 1 reports both modes: "update only" and "+ measurement"
-        u2 = plain_leg(binding, 2, 4096, workloads.TC_2D, 2, args.warmup, args.steps,
-                       measure=False)
+        u2 = plain_leg(binding, 2, 4096, workloads.TC_2D, 2, max(args.warmup, MIN_THERM[2]),
+                       args.steps, measure=False)
         extra["plain_2d_L4096_update_only"] = {k: v for k, v in u2.items()
                                                if k not in ("records", "checkpoint")}
         if "plain3d" in legs:
-            u3 = plain_leg(binding, 3, 256, workloads.T_3D, 3, 3 * args.warmup, 5 * args.steps,
-                           measure=False)
+            u3 = plain_leg(binding, 3, 256, workloads.T_3D, 3, max(3 * args.warmup, MIN_THERM[3]),
+                           5 * args.steps, measure=False)
             extra["plain_3d_L256_update_only"] = {k: v for k, v in u3.items()
                                                   if k not in ("records", "checkpoint")}
     if "c1" in legs:
@@ -556,7 +573,7 @@ def main():
     if "c4" in legs:
         extra["c4_mixed_batch"] = c4_leg(binding, workloads, args.c4_updates)
     if "serve" in legs:
-        extra["serve_stream"] = serve_leg(workloads)
+        extra["serve_stream"] = serve_leg(binding, workloads)
     copy_gbs = copy_peak_gbs()
     log("device copy: %.0f GB/s" % copy_gbs)
     for leg in extra.values():
@@ -584,7 +601,9 @@ def main():
         "config": {
             "workload": "2d_L4096_Tc_plain",
             "dim": 2, "L": 4096, "T": workloads.TC_2D, "J": 1.0, "seed": 2,
-            "start": "ordered, thermalised for `warmup` updates at T_c",
+            "start": "ordered, thermalised at T_c before the timed updates",
+            "thermalisation_updates": main_leg["warmup"],
+            "mean_cluster_size_last_thermalisation": main_leg["therm_mean_csize"],
             "path": ("plain one-lattice launch path (multi-workgroup team kernel)" if team
                      else "plain one-lattice launch path (one-workgroup kernel)"),
             "measurement": "E and M after every update",

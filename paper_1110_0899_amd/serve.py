@@ -21,7 +21,7 @@ def percentile(xs, q):
 
 def run_stream(jobs, quantum_ms: float = 5.0, hbm_budget: int = 0, max_slots: int = 0,
                max_wall_s: float | None = None, keep_records: bool = False,
-               update_only: bool = True, progress=None):
+               update_only: bool = False, keep_finish_times: bool = False, progress=None):
     """Serve `jobs` (objects with dim, L, J, T, seed, n_updates, arrival_s).
 
     Returns a dict with per-job latency, p50/p99, aggregate added spins/s and
@@ -29,7 +29,7 @@ def run_stream(jobs, quantum_ms: float = 5.0, hbm_budget: int = 0, max_slots: in
     and the loop drains what was submitted."""
     order = sorted(range(len(jobs)), key=lambda k: jobs[k].arrival_s)
     srv = binding.Server(hbm_budget, max_slots)
-    arrival, latency, records, index_of = {}, {}, {}, {}
+    arrival, latency, records, index_of, finish = {}, {}, {}, {}, []
     added = 0
     t0 = time.perf_counter()
     i = 0
@@ -65,6 +65,7 @@ def run_stream(jobs, quantum_ms: float = 5.0, hbm_budget: int = 0, max_slots: in
         for jid in srv.finished():
             rec = srv.take(jid)
             latency[jid] = done_t - arrival[jid]
+            finish.append(done_t)
             added += int(rec["csize"].sum())
             if keep_records:
                 records[index_of[jid]] = rec
@@ -82,17 +83,26 @@ def run_stream(jobs, quantum_ms: float = 5.0, hbm_budget: int = 0, max_slots: in
         "gpu_ms": stats["gpu_ms"], "slots": stats["slots"],
         "budget_bytes": stats["budget_bytes"],
         "records": records,
+        "finish_s": finish if keep_finish_times else None,
     }
 
 
-def capacity(jobs, quantum_ms: float = 5.0, hbm_budget: int = 0, progress=None) -> dict:
-    """Estimate the job rate that keeps every workgroup slot busy.
+def capacity(jobs, quantum_ms: float = 5.0, hbm_budget: int = 0, update_only: bool = False,
+             progress=None) -> dict:
+    """Saturated throughput of the loop, measured.
 
-    All of `jobs` are queued at time 0 (fewer than the slots, so each starts
-    at once and its completion time is its service time); by Little's law a
-    stream keeps `slots` jobs resident at rate slots / mean service time."""
+    Every job of `jobs` (more than the loop's slots) is queued at time 0, so
+    the loop runs full until the queue empties; the capacity is the rate of
+    completions between the first and the last fifth of them (the start-up
+    ramp and the drain tail excluded)."""
     closed = [type(j)(**{**j.as_dict(), "arrival_s": 0.0}) for j in jobs]
-    r = run_stream(closed, quantum_ms=quantum_ms, hbm_budget=hbm_budget, progress=progress)
-    service = r["mean_latency_s"]
-    return {"jobs_per_s": r["slots"] / service, "mean_service_s": service,
-            "slots": r["slots"], "closed_batch_jobs_per_s": r["jobs"] / r["wall_s"]}
+    r = run_stream(closed, quantum_ms=quantum_ms, hbm_budget=hbm_budget, update_only=update_only,
+                   keep_finish_times=True, progress=progress)
+    fin = np.sort(np.asarray(r["finish_s"], dtype=np.float64))
+    n = len(fin)
+    lo, hi = n // 5, (4 * n) // 5
+    rate = (hi - lo) / (fin[hi] - fin[lo]) if hi > lo and fin[hi] > fin[lo] else n / r["wall_s"]
+    return {"jobs_per_s": float(rate), "jobs": n, "slots": r["slots"],
+            "closed_batch_wall_s": r["wall_s"], "closed_batch_jobs_per_s": n / r["wall_s"],
+            "closed_batch_added_per_s": r["added_per_s"],
+            "window": "completions %d..%d of %d" % (lo, hi, n)}

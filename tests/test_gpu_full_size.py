@@ -89,3 +89,29 @@ def test_batched_full_size_sampled(dim, L, T, seed):
             ref = oracle.run(dim, L, thr, j.seed, 0, j.n_updates, S)
             assert (as_array(b.records(i)) == ref).all(), i
             assert (b.spins(i) == S).all(), i
+
+
+@pytest.mark.parametrize("dim,L,T,seed", SIZES)
+def test_plain_thermalised_window(dim, L, T, seed):
+    # the headline's state: ordered start thermalised at T_c on the default
+    # path, then a window of updates checkpointed and replayed by the oracle
+    print("case full-size thermalised window dim=%d L=%d" % (dim, L), flush=True)
+    thr = oracle.threshold(1.0, T)
+    N = L ** dim
+    n_therm, n_win = (300, 10) if dim == 2 else (1000, 10)
+    with binding.Simulation(dim, L, 1.0, T, seed) as sim:
+        sim.set_spins(np.ones(N, dtype=np.int8), 0)
+        sim.run(n_therm)
+        therm = as_array(sim.observables())
+        S = sim.spins()
+        t = sim.info().t
+        sim.run(n_win)
+        got = as_array(sim.observables())
+        ref = oracle.run(dim, L, thr, seed, t, n_win, S)
+        assert (got == ref).all()
+        assert (sim.spins() == S).all()
+    # invariants along the thermalisation run: |dM| = 2 |C| every update
+    dM = np.abs(np.diff(np.concatenate([[N], therm[:, 1]])))
+    assert (dM == 2 * therm[:, 2]).all()
+    # the window is at equilibrium cluster sizes, not the ordering transient
+    assert ref[:, 2].mean() < 0.5 * N

@@ -1,6 +1,7 @@
-"""Batched and serving forms: every replica / job gives exactly the records it
-gives alone (same seed, same update indices), whatever else shares the
-launch, and the serving loop respects its HBM budget."""
+"""Batched and serving forms against the CPU oracle: every replica / job gives
+exactly the oracle's records and spins for its own seed and update indices
+(so the same result alone and in any mix), whatever else shares the launch,
+and the serving loop respects its HBM budget."""
 import numpy as np
 import pytest
 import torch
@@ -17,13 +18,26 @@ def as_array(rec):
     return np.stack([rec["bond_sum"], rec["mag"], rec["csize"]], axis=1)
 
 
-def alone(job, start=0):
-    with binding.Simulation(job.dim, job.L, job.J, job.T, job.seed) as sim:
-        sim.set_path(binding.PATH_SINGLE)
-        if start:
-            sim.set_spins(np.full(job.L ** job.dim, start, dtype=np.int8), 0)
-        sim.run(job.n_updates)
-        return as_array(sim.observables()), sim.spins()
+_REFERENCE = {}
+
+
+def reference(job, start=0):
+    """The oracle's records and final spins of `job` run alone from its own
+    start (iid from its seed, or ordered)."""
+    key = (job.dim, job.L, job.J, job.T, job.seed, job.n_updates, start)
+    if key not in _REFERENCE:
+        _REFERENCE[key] = _reference(job, start)
+    rec, S = _REFERENCE[key]
+    return rec.copy(), S.copy()
+
+
+def _reference(job, start):
+    thr = oracle.threshold(job.J, job.T)
+    N = job.L ** job.dim
+    S = (oracle.init_spins(job.dim, job.L, job.seed) if start == 0
+         else np.full(N, start, dtype=np.int8))
+    rec = oracle.run(job.dim, job.L, thr, job.seed, 0, job.n_updates, S)
+    return rec, S
 
 
 def mixed_jobs(n, seed=0):
@@ -47,7 +61,7 @@ def gpu():
     binding.load()
 
 
-def test_batch_budgeted_quanta_match_alone():
+def test_batch_budgeted_quanta_match_oracle():
     jobs = mixed_jobs(24, seed=1)
     with binding.Batch(jobs) as b:
         for _ in range(200):
@@ -56,7 +70,7 @@ def test_batch_budgeted_quanta_match_alone():
             b.run(7)
         for i, j in enumerate(jobs):
             got = as_array(b.records(i))
-            ref, S = alone(j)
+            ref, S = reference(j)
             assert (got == ref).all(), i
             assert (b.spins(i) == S).all(), i
 
@@ -78,7 +92,7 @@ def test_mixed_c4_style_batch_against_oracle():
             assert (b.spins(i) == S).all(), i
 
 
-def test_server_alone_vs_mix():
+def test_server_mix_matches_oracle():
     jobs = mixed_jobs(40, seed=2)
     results = {}
     with binding.Server() as srv:
@@ -95,7 +109,7 @@ def test_server_alone_vs_mix():
         st = srv.stats()
     assert st["running"] == 0 and st["queued"] == 0
     for k, j in enumerate(jobs):
-        ref, _ = alone(j)
+        ref, _ = reference(j)
         assert (results[k] == ref).all(), k
 
 
@@ -114,7 +128,7 @@ def test_server_admission_by_footprint():
             for jid in srv.finished():
                 results[ids[jid]] = as_array(srv.take(jid))
     for k, j in enumerate(jobs):
-        ref, _ = alone(j)
+        ref, _ = reference(j)
         assert (results[k] == ref).all(), k
 
 
@@ -135,6 +149,91 @@ def test_server_update_only_jobs():
             for jid in srv.finished():
                 results[ids[jid]] = as_array(srv.take(jid))
     for k, j in enumerate(jobs):
-        ref, _ = alone(j)
+        ref, _ = reference(j)
         assert (results[k][:, 0] == binding.NOT_MEASURED).all()
         assert (results[k][:, 1:] == ref[:, 1:]).all(), k
+
+
+def test_c4_replica_set_thermalised_windows_against_oracle():
+    # the mixed replica set itself (256 square lattices L in {64..1024},
+    # T in [2.0, 2.6]; 64 simple-cubic L in {32, 64, 128}, T in [4.3, 4.7]),
+    # in the batched launch: the first updates from the random start, then a
+    # window after 1500 updates of every replica, replayed by the oracle from
+    # the GPU's checkpoint of sampled replicas (the coldest and largest
+    # lattices of each dimension, where the cluster fills most of the lattice,
+    # and a seeded sample of the rest)
+    jobs = workloads.c4_jobs(1600)
+    rng = np.random.default_rng(44)
+    big2 = sorted((k for k, j in enumerate(jobs) if j.dim == 2 and j.L == 1024),
+                  key=lambda k: jobs[k].T)[:2]
+    big3 = sorted((k for k, j in enumerate(jobs) if j.dim == 3 and j.L == 128),
+                  key=lambda k: jobs[k].T)[:2]
+    sample = sorted(set(big2 + big3) | set(int(k) for k in rng.choice(len(jobs), 6, replace=False)))
+    print("case c4 sample %s" % sample, flush=True)
+    with binding.Batch(jobs) as b:
+        b.run(5)
+        for k in sample:
+            j = jobs[k]
+            thr = oracle.threshold(j.J, j.T)
+            S = oracle.init_spins(j.dim, j.L, j.seed)
+            ref = oracle.run(j.dim, j.L, thr, j.seed, 0, 5, S)
+            assert (as_array(b.records(k)) == ref).all(), k
+            assert (b.spins(k) == S).all(), k
+        b.run(1495)
+        ckpt = {k: b.spins(k) for k in sample}
+        for k in range(len(jobs)):
+            b.records(k)                       # drain the thermalisation records
+        b.run(6)
+        for k in sample:
+            j = jobs[k]
+            assert b.progress(k)[1] == 1506
+            thr = oracle.threshold(j.J, j.T)
+            S = ckpt[k].copy()
+            ref = oracle.run(j.dim, j.L, thr, j.seed, 1500, 6, S)
+            assert (as_array(b.records(k)) == ref).all(), k
+            assert (b.spins(k) == S).all(), k
+    # the coldest square lattice is in the ordered phase: its window holds
+    # clusters of most of its sites
+    k = big2[0]
+    assert jobs[k].T < 2.1
+
+
+def c5_sample():
+    """Jobs of the serving stream's shapes (2D L log-uniform 64..4096, 3D
+    32..256, T within 2 % of T_c): for each dimension the largest lattice
+    among the jobs with at most 300 updates, and a seeded sample of jobs
+    whose N * n_updates the oracle replays in seconds."""
+    stream = workloads.c5_stream(n_jobs=400, rate_per_s=1.0, seed=5)
+    pick = []
+    for dim in (2, 3):
+        cand = [j for j in stream if j.dim == dim and j.n_updates <= 300]
+        pick.append(max(cand, key=lambda j: j.L))
+    small = [j for j in stream if j.L ** j.dim * j.n_updates <= 3e7 and j not in pick]
+    rng = np.random.default_rng(55)
+    pick += [small[int(k)] for k in rng.choice(len(small), 10, replace=False)]
+    return pick
+
+
+@pytest.mark.parametrize("update_only", [False, True])
+def test_c5_shaped_jobs_through_server_against_oracle(update_only):
+    jobs = c5_sample()
+    print("case c5 update_only=%d: %s" % (update_only, [(j.dim, j.L, j.n_updates) for j in jobs]),
+          flush=True)
+    results = {}
+    with binding.Server() as srv:
+        ids = {}
+        for k, j in enumerate(jobs):           # arrivals between quanta
+            ids[srv.submit(j, update_only=update_only)] = k
+            srv.step(0.5)
+        while len(results) < len(jobs):
+            srv.step(2.0)
+            for jid in srv.finished():
+                results[ids[jid]] = as_array(srv.take(jid))
+    assert max(j.L for j in jobs if j.dim == 2) > 1000
+    for k, j in enumerate(jobs):
+        ref, _ = reference(j)
+        if update_only:
+            assert (results[k][:, 0] == binding.NOT_MEASURED).all()
+            assert (results[k][:, 1:] == ref[:, 1:]).all(), k
+        else:
+            assert (results[k] == ref).all(), k
