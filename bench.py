@@ -455,7 +455,8 @@ def profile_only(args, binding, workloads):
         torch.cuda.synchronize()
         r = {"leg": "copy", "bytes_read": n, "bytes_written": n}
     elif leg in ("plain2d", "plain3d"):
-        path = {"auto": None, "single": binding.PATH_SINGLE, "team": binding.PATH_TEAM}[args.path]
+        path = {"auto": None, "single": binding.PATH_SINGLE, "team": binding.PATH_TEAM,
+                "lds": binding.PATH_LDS}[args.path]
         dim, L, T, seed = ((2, 4096, workloads.TC_2D, 2) if leg == "plain2d"
                            else (3, 256, workloads.T_3D, 3))
         r = plain_leg(binding, dim, L, T, seed, max(args.warmup, MIN_THERM[dim]), args.steps,
@@ -490,7 +491,7 @@ def build_parser() -> argparse.ArgumentParser:
     ap.add_argument("--tiles", default="512,2048",
                     help="workgroup size, LDS ring entries of a profiled batch leg (the full "
                          "benchmark takes them from the autotuner)")
-    ap.add_argument("--path", default="auto", choices=("auto", "single", "team"),
+    ap.add_argument("--path", default="auto", choices=("auto", "single", "team", "lds"),
                     help="growth path of a profiled plain leg (default: the library's choice)")
     ap.add_argument("--profile-leg", default=None,
                     choices=("plain2d", "plain3d", "batch2d", "batch3d", "copy"),

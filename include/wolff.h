@@ -49,6 +49,7 @@ extern "C" {
 #define WOLFF_EDEVICE    -3   /* HIP runtime error (message in wolff_last_error)    */
 #define WOLFF_ERANGE     -4   /* update index would pass 2^32 - 2                   */
 #define WOLFF_ESTATE     -5   /* a device-side consistency check failed             */
+#define WOLFF_EABORTED   -6   /* updates stopped on request (wolff_abort)           */
 
 /* bond_sum value of a record taken with measurement switched off */
 #define WOLFF_NOT_MEASURED INT64_MIN
@@ -82,13 +83,54 @@ typedef struct {
 
 typedef struct wolff_sim wolff_sim;
 
-/* Create a lattice of L^dim spins, iid +-1 from `seed` (update index t = 0).
- * dim in {2, 3}; L >= 2; L^dim < 2^32; J > 0 and T > 0 finite.
- * Allocates about 5 bytes per site of device memory (spins and the overflow
- * stack of the one-workgroup path), plus 8 bytes per site for the
- * multi-workgroup queue on the first team-path run.
- * Synchronises before returning.  *out is set only on success. */
+/* Create a lattice of L^dim spins, iid +-1 from `seed` (update index t = 0):
+ * the problem of Section 2 (the Ising Hamiltonian with coupling J on the
+ * periodic square or simple-cubic lattice of linear size L, at temperature
+ * T; Section 5 runs it at the critical temperatures).
+ * dim in {2, 3}; L >= 2; L^dim < 2^32; J > 0 and T > 0 finite (WOLFF_EINVAL
+ * otherwise).  Allocates about 5 bytes per site of device memory (spins and
+ * the overflow stack of the one-workgroup path), plus 8 bytes per site for
+ * the multi-workgroup queue on the first team-path run (WOLFF_ENOMEM when
+ * it does not fit).  Synchronises before returning.  *out is set only on
+ * success; the handle owns all its device memory. */
 int wolff_create(int dim, int L, double J, double T, uint64_t seed, wolff_sim **out);
+
+/* Device buffers that the caller allocates (e.g. torch tensors) and keeps
+ * alive until wolff_destroy; the library frees none of them. */
+typedef struct {
+    int8_t       *spins;          /* >= ((L^dim + 3) / 4) * 4 bytes, 16-byte aligned:
+                                     the lattice in site order (x fastest), int8
+                                     +1 / -1.  Between calls (once the handle's
+                                     stream is idle) it holds the spins at the
+                                     handle's update index. */
+    uint32_t     *overflow;       /* >= 4 L^dim bytes, 4-byte aligned: the frontier
+                                     overflow stack of the one-workgroup path */
+    wolff_record *records;        /* record_capacity records, 8-byte aligned: the
+                                     record of the k-th update since the buffer
+                                     was last drained is records[k] */
+    uint64_t      record_capacity;/* >= 1 */
+    void         *team_queue;     /* NULL, or >= 8 L^dim bytes, 8-byte aligned: the
+                                     multi-workgroup queue (NULL: the library
+                                     allocates it on the first team-path run) */
+    uint64_t      t0;             /* update index of the state in `spins` when
+                                     WOLFF_BUFFERS_KEEP_SPINS is set */
+    uint32_t      flags;          /* 0 or WOLFF_BUFFERS_KEEP_SPINS */
+    uint32_t      reserved;       /* 0 */
+} wolff_buffers;
+
+/* flags: the spins buffer already holds the state (+1 / -1 bytes) at update
+ * index t0; without it the library fills it iid from the seed (t = 0). */
+#define WOLFF_BUFFERS_KEEP_SPINS 1u
+
+/* wolff_create on caller-owned device buffers (the problem statement of
+ * Section 2, as wolff_create).  The lattice is stored in site order in
+ * `spins`, so the caller's tensor is the lattice itself.  wolff_run fails
+ * with WOLFF_EINVAL when its records would not fit in the record buffer
+ * beside the pending ones (drain them with wolff_observables).
+ * WOLFF_EINVAL for a NULL or misaligned buffer, a record capacity of 0 or
+ * unknown flags; WOLFF_ERANGE for t0 > 2^32 - 2; otherwise as wolff_create. */
+int wolff_create_ex(int dim, int L, double J, double T, uint64_t seed,
+                    const wolff_buffers *buffers, wolff_sim **out);
 
 /* The q-state Potts model, H = -J sum_<ij> delta(s_i, s_j), colours
  * 0 .. q-1 (the extension Section 6 calls straightforward), 2 <= q <= 127:
@@ -106,46 +148,87 @@ int wolff_create(int dim, int L, double J, double T, uint64_t seed, wolff_sim **
 int wolff_create_potts(int dim, int L, int q, double J, double T, uint64_t seed,
                        wolff_sim **out);
 
-/* Release the handle and its device memory (waits for its stream). NULL is ok. */
+/* Release the handle and its device memory (waits for its stream). NULL is
+ * ok.  Buffers given to wolff_create_ex stay the caller's. */
 int wolff_destroy(wolff_sim *s);
 
-/* Enqueue n_updates Wolff updates (Section 2, steps (i)-(v)); asynchronous.
- * Appends one record per update.  WOLFF_ERANGE if t + n_updates > 2^32 - 2. */
+/* Enqueue n_updates Wolff updates (Section 2, steps (i)-(v), the cluster
+ * grown frontier-parallel as in Section 4, step (iii')); asynchronous.
+ * Appends one record per update.  WOLFF_ERANGE if t + n_updates > 2^32 - 2;
+ * WOLFF_EABORTED (nothing enqueued) if a stop request from wolff_abort cut
+ * earlier work short and was not yet reported. */
 int wolff_run(wolff_sim *s, uint64_t n_updates);
 
-/* Wait for the stream, then move up to `cap` pending records, oldest first,
- * into out[]; *n_out receives the number moved.  Returns WOLFF_ESTATE if a
- * device-side consistency check (a recount of the magnetisation or of the
- * bond sum disagreeing with the tracked value) failed. */
+/* Wait for the stream, then move up to `cap` pending records (the energy
+ * and magnetisation measured after every update, Section 5, "+
+ * measurement"), oldest first, into out[]; *n_out receives the number
+ * moved.  Returns WOLFF_ESTATE if a device-side consistency check (a
+ * recount of the magnetisation or of the bond sum disagreeing with the
+ * tracked value) failed, WOLFF_EABORTED (after moving the records of the
+ * updates that ran) if a stop request cut the work short. */
 int wolff_observables(wolff_sim *s, wolff_record *out, uint64_t cap, uint64_t *n_out);
 
-/* Wait for all work enqueued on the handle's stream. */
+/* Wait for all work enqueued on the handle's stream (the end of step (v)
+ * of Section 2 for every enqueued update).  WOLFF_EABORTED once if a stop
+ * request cut the work short. */
 int wolff_synchronize(wolff_sim *s);
 
-/* Current parameters and state (synchronises). */
+/* Ask the updates enqueued on this handle to stop at the next update
+ * boundary: the update in progress completes, the ones after it do not
+ * start (a running one-workgroup launch polls the request after every
+ * update, a team-path update before it starts).  Safe to call from another
+ * host thread while the device works.  The state stays exact: spins, the
+ * update index (the first update that did not run) and the records of the
+ * updates that ran.  The next call that waits for the handle's stream
+ * (wolff_synchronize, wolff_observables, wolff_get_info, wolff_get_spins,
+ * wolff_set_spins, wolff_set_measure, wolff_run) clears the request and
+ * returns WOLFF_EABORTED once if updates were skipped; the handle stays
+ * usable.  For callers that need to end long runs early (Section 5's runs
+ * of 10^4 updates per configuration). */
+int wolff_abort(wolff_sim *s);
+
+/* Current parameters (Section 2: L, d, J, T and the bond threshold of step
+ * (ii)) and state (update index, the last measured E and M of Section 5);
+ * synchronises.  WOLFF_EABORTED as wolff_synchronize (after filling *out). */
 int wolff_get_info(wolff_sim *s, wolff_info *out);
 
-/* Copy the N spins (int8, +-1, site order) to host memory; n must equal N. */
+/* Copy the N spins (int8, +-1 Ising / colours Potts, site order) of the
+ * lattice after the latest update (Section 2, step (v)) to host memory; n
+ * must equal N (WOLFF_EINVAL otherwise).  Synchronises. */
 int wolff_get_spins(wolff_sim *s, int8_t *host, uint64_t n);
 
-/* Replace the spins (n == N, values +-1) and set the next update index to t
- * (checkpoint resume: the state is exactly (spins, t)).  Pending records
- * are dropped and the observables recomputed. */
+/* Replace the spins (n == N, values +-1; Potts: colours in [0, q)) and set
+ * the next update index to t (checkpoint resume: the state of the Markov
+ * chain of Section 2 is exactly (spins, t)).  Pending records are dropped
+ * and the observables recomputed.  WOLFF_EINVAL for other values,
+ * WOLFF_ERANGE for t > 2^32 - 2. */
 int wolff_set_spins(wolff_sim *s, const int8_t *host, uint64_t n, uint64_t t);
 
-/* 1: bond_sum after every update (the paper's "+ measurement"): for even L
- * the one-workgroup path updates it exactly from counts taken while the
- * cluster grows (and recounts it over the lattice every 32 updates as a
- * check); the team path and odd L recount it over the lattice after every
- * update; 0: "update only", bond_sum = WOLFF_NOT_MEASURED.
+/* The two columns of Section 5's Tables 1 and 2.
+ * 1: bond_sum after every update (the paper's "+ measurement"): the
+ * one-workgroup path updates it exactly from counts taken while the
+ * cluster grows (Ising; it recounts it over the lattice every 32 updates as
+ * a check); the LDS path recounts its bit lattice in LDS; the team path and
+ * Potts lattices recount it over the lattice after every update; 0: "update
+ * only", bond_sum = WOLFF_NOT_MEASURED.
  * mag and csize are exact in both modes.  Default 1. */
 int wolff_set_measure(wolff_sim *s, int on);
 
 /* Use the caller's HIP stream (a hipStream_t, e.g. torch's current stream)
- * for all later work; NULL returns to the handle's own stream. */
+ * for all later work; NULL returns to the handle's own stream.  Waits for
+ * the previous stream first.  (Plumbing: no passage of the paper.) */
 int wolff_set_stream(wolff_sim *s, void *hip_stream);
 
-/* Growth path: WOLFF_PATH_SINGLE runs every update in one workgroup (LDS
+/* Growth path (the frontier-parallel growth of Section 4; Section 6 and
+ * Table 3 treat small frontiers separately, as this choice does):
+ * WOLFF_PATH_LDS (Ising only) keeps the lattice in LDS as one bit per spin
+ * for a whole launch of many updates, split into slabs of whole rows (2D)
+ * or planes (3D), one workgroup per slab (a lattice of at most 2^20 spins
+ * fits one workgroup); gathers and claims are LDS accesses and only bonds
+ * that cross a slab boundary go through global memory; WOLFF_EINVAL for
+ * lattices it cannot hold (a row or plane above the slab size, or more than
+ * 64 slabs).
+ * WOLFF_PATH_SINGLE runs every update in one workgroup (LDS
  * frontier queue, one launch for many updates); WOLFF_PATH_TEAM runs each
  * update on `workgroups` cooperating workgroups (0 = library default) that
  * share an atomic-counter frontier.  WOLFF_PATH_AUTO takes the path with
@@ -159,21 +242,32 @@ int wolff_set_stream(wolff_sim *s, void *hip_stream);
 #define WOLFF_PATH_AUTO   0
 #define WOLFF_PATH_SINGLE 1
 #define WOLFF_PATH_TEAM   2
+#define WOLFF_PATH_LDS    3
 int wolff_set_path(wolff_sim *s, int path, int workgroups);
 
 /* Workgroup size and LDS frontier ring entries of the one-workgroup path
- * (same ranges as wolff_batch_set_tiles).  Default: 64 threads up to 4096
+ * (the paper's block size and shared-memory queue, Section 4; WOLFF_EINVAL
+ * outside the ranges)
+ * - same ranges as wolff_batch_set_tiles.  Default: 64 threads up to 4096
  * sites, 128 up to 16384, 256 below 2^20 (2048 entries), 512 from 2^20
  * sites (4096 entries). */
 int wolff_set_tiles(wolff_sim *s, int wg, int queue_entries);
 
-/* Team path: replay a captured HIP graph of `chunk` updates (the seed,
+/* LDS-resident path (WOLFF_PATH_LDS): the most spins one workgroup holds
+ * as bits in LDS (its slab of whole rows / planes); a power of two in
+ * [2^10, 2^20], default 2^20.  Smaller slabs spread a lattice over more
+ * workgroups (the paper's blocks, Section 4).  WOLFF_EINVAL otherwise. */
+int wolff_set_lds_slab(wolff_sim *s, uint32_t slab_bits);
+
+/* Team path: replay a captured HIP graph of `chunk` updates (step (v) of
+ * Section 2 repeated on the device without host launches; the seed,
  * growth and measurement launches of each) instead of launching them one by
  * one; 0 launches every kernel directly.  Default 16.  Graphs are not used
  * while kernel timing (wolff_profile) is on. */
 int wolff_set_graph(wolff_sim *s, int chunk);
 
-/* Kernel timing with HIP events on the handle's stream.  While on, every
+/* Kernel timing with HIP events on the handle's stream (the per-update
+ * times of Section 5, Tables 1 and 2).  While on, every
  * launch of the cluster-growth kernel and of the measurement kernel is
  * bracketed by events; wolff_profile_read synchronises and returns the summed
  * milliseconds and launch counts since the last reset. */
@@ -181,17 +275,23 @@ int wolff_profile(wolff_sim *s, int on);
 int wolff_profile_read(wolff_sim *s, double *grow_ms, uint64_t *grow_launches,
                        double *measure_ms, uint64_t *measure_launches);
 
-/* Static description of an error code. */
+/* Static description of an error code (never NULL).  (Plumbing: no
+ * passage of the paper.) */
 const char *wolff_strerror(int code);
 
-/* Message of the calling thread's most recent failure ("" if none). */
+/* Message of the calling thread's most recent failure ("" if none); valid
+ * until that thread's next failing call.  (Plumbing.) */
 const char *wolff_last_error(void);
 
 /* ------------------------------------------------------- batched replicas */
 /* Many independent lattices (any mix of dim, L, J, T, seed) advanced by one
  * persistent launch per wolff_batch_run: each workgroup takes whole replicas
  * from an atomic work counter, longest expected work first.  Every replica
- * follows exactly the stream it would follow alone through wolff_sim. */
+ * follows exactly the stream it would follow alone through wolff_sim (each
+ * runs the update of Section 2).  Section 5's studies run many (L, T)
+ * points, e.g. the Binder-ratio scan of its Fig. 2, and its Section 1
+ * notes that many lattices are simulated independently; this form runs
+ * them in one launch.  Not a passage of the paper's method itself. */
 typedef struct {
     int32_t  dim;
     int32_t  L;
@@ -214,15 +314,20 @@ typedef struct {
 
 typedef struct wolff_batch wolff_batch;
 
-/* Allocate and initialise n_jobs replicas (synchronises). */
+/* Allocate and initialise n_jobs replicas (synchronises).  WOLFF_EINVAL
+ * for a bad job (same rules as wolff_create) or n_jobs < 1, WOLFF_ERANGE
+ * for n_updates > 2^32 - 2, WOLFF_ENOMEM when the lattices do not fit. */
 int wolff_batch_create(const wolff_job *jobs, int n_jobs, wolff_batch **out);
+/* Release the batch and its device memory (waits for its stream). */
 int wolff_batch_destroy(wolff_batch *b);
 
 /* Advance every replica with updates left by at most max_updates (0 = all
- * that are left) in one launch; asynchronous. */
+ * that are left) in one launch (Section 2, steps (i)-(v), per replica);
+ * asynchronous. */
 int wolff_batch_run(wolff_batch *b, uint64_t max_updates);
 
-/* Pending records of replica `job` (synchronises), oldest first. */
+/* Pending records of replica `job` (synchronises), oldest first (Section
+ * 5, "+ measurement"); WOLFF_ESTATE if a device-side check failed for it. */
 int wolff_batch_records(wolff_batch *b, int job, wolff_record *out, uint64_t cap,
                         uint64_t *n_out);
 
@@ -232,11 +337,14 @@ int wolff_batch_progress(wolff_batch *b, int job, uint64_t *left, uint64_t *t);
 /* Spins of replica `job` (n must equal its N; synchronises). */
 int wolff_batch_get_spins(wolff_batch *b, int job, int8_t *host, uint64_t n);
 
+/* Measurement for every replica, as wolff_set_measure (Section 5's two
+ * columns); synchronises. */
 int wolff_batch_set_measure(wolff_batch *b, int on);
 
 /* 1 (default): each wolff_batch_run replays a captured HIP graph of its
  * launches (one graph per distinct launch configuration); 0: direct launches. */
 int wolff_batch_set_graph(wolff_batch *b, int on);
+/* As wolff_set_stream. */
 int wolff_batch_set_stream(wolff_batch *b, void *hip_stream);
 
 /* Workgroup size / LDS queue of the batched kernel, picked by the tuner:
@@ -250,7 +358,9 @@ int wolff_batch_set_tiles(wolff_batch *b, int wg, int queue_entries);
 int wolff_batch_last_ms(wolff_batch *b, double *ms);
 
 /* ------------------------------------------------------------ serving loop */
-/* A request loop that keeps lattices resident in HBM and advances every
+/* Serving form (not a passage of the paper: each job runs the update of
+ * Section 2 and returns the records of Section 5).
+ * A request loop that keeps lattices resident in HBM and advances every
  * resident job in time-bounded quanta, each one persistent launch of the
  * batched kernel (continuous batching).  Jobs are admitted first-in
  * first-out while a workgroup slot and their HBM footprint are free

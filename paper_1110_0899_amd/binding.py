@@ -20,9 +20,9 @@ import torch  # noqa: F401  (one HIP runtime per process: torch's)
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBRARY = os.path.join(HERE, "libwolff.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ERANGE, ESTATE = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EDEVICE, ERANGE, ESTATE, EABORTED = 0, -1, -2, -3, -4, -5, -6
 NOT_MEASURED = -(2 ** 63)
-PATH_AUTO, PATH_SINGLE, PATH_TEAM = 0, 1, 2
+PATH_AUTO, PATH_SINGLE, PATH_TEAM, PATH_LDS = 0, 1, 2, 3
 
 
 class WolffError(RuntimeError):
@@ -42,6 +42,16 @@ class Info(ctypes.Structure):
                 ("mag", ctypes.c_int64), ("bond_sum", ctypes.c_int64),
                 ("records_pending", ctypes.c_uint64), ("q", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
+
+
+class Buffers(ctypes.Structure):
+    _fields_ = [("spins", ctypes.c_void_p), ("overflow", ctypes.c_void_p),
+                ("records", ctypes.c_void_p), ("record_capacity", ctypes.c_uint64),
+                ("team_queue", ctypes.c_void_p), ("t0", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+BUFFERS_KEEP_SPINS = 1
 
 
 class JobDesc(ctypes.Structure):
@@ -74,7 +84,9 @@ _D = ctypes.c_double
 SIGNATURES = {
     "wolff_create": (_I, [_I, _I, _D, _D, _U64, ctypes.POINTER(_P)]),
     "wolff_create_potts": (_I, [_I, _I, _I, _D, _D, _U64, ctypes.POINTER(_P)]),
+    "wolff_create_ex": (_I, [_I, _I, _D, _D, _U64, ctypes.POINTER(Buffers), ctypes.POINTER(_P)]),
     "wolff_destroy": (_I, [_P]),
+    "wolff_abort": (_I, [_P]),
     "wolff_run": (_I, [_P, _U64]),
     "wolff_observables": (_I, [_P, _P, _U64, ctypes.POINTER(_U64)]),
     "wolff_synchronize": (_I, [_P]),
@@ -85,6 +97,7 @@ SIGNATURES = {
     "wolff_set_stream": (_I, [_P, _P]),
     "wolff_set_path": (_I, [_P, _I, _I]),
     "wolff_set_graph": (_I, [_P, _I]),
+    "wolff_set_lds_slab": (_I, [_P, ctypes.c_uint32]),
     "wolff_set_tiles": (_I, [_P, _I, _I]),
     "wolff_profile": (_I, [_P, _I]),
     "wolff_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_U64),
@@ -152,10 +165,24 @@ class Simulation:
     """One lattice: wolff_create / wolff_run / wolff_observables; with q >= 2
     the q-state Potts model (wolff_create_potts)."""
 
-    def __init__(self, dim: int, L: int, J: float, T: float, seed: int, q: int = 0):
+    def __init__(self, dim: int, L: int, J: float, T: float, seed: int, q: int = 0,
+                 buffers: dict | None = None):
+        """buffers: caller-owned device memory for wolff_create_ex, a dict
+        with the raw device addresses "spins", "overflow", "records" (e.g.
+        tensor.data_ptr()), "record_capacity", optional "team_queue", and
+        optional "t0" (the spins buffer then already holds the state at
+        update t0)."""
         lib = load()
         h = ctypes.c_void_p()
-        if q:
+        if buffers is not None:
+            keep = "t0" in buffers
+            b = Buffers(int(buffers["spins"]), int(buffers["overflow"]), int(buffers["records"]),
+                        int(buffers["record_capacity"]),
+                        int(buffers["team_queue"]) if buffers.get("team_queue") else None,
+                        int(buffers.get("t0", 0)), BUFFERS_KEEP_SPINS if keep else 0, 0)
+            _check(lib.wolff_create_ex(dim, L, float(J), float(T), int(seed), ctypes.byref(b),
+                                       ctypes.byref(h)), "wolff_create_ex")
+        elif q:
             _check(lib.wolff_create_potts(dim, L, int(q), float(J), float(T), int(seed),
                                           ctypes.byref(h)), "wolff_create_potts")
         else:
@@ -198,6 +225,11 @@ class Simulation:
     def synchronize(self):
         _check(load().wolff_synchronize(self._h), "wolff_synchronize")
 
+    def abort(self):
+        """Stop the enqueued updates at the next update boundary (callable
+        from another thread)."""
+        _check(load().wolff_abort(self._h), "wolff_abort")
+
     def info(self) -> Info:
         inf = Info()
         _check(load().wolff_get_info(self._h, ctypes.byref(inf)), "wolff_get_info")
@@ -221,6 +253,9 @@ class Simulation:
 
     def set_path(self, path: int, workgroups: int = 0):
         _check(load().wolff_set_path(self._h, path, workgroups), "wolff_set_path")
+
+    def set_lds_slab(self, slab_bits: int):
+        _check(load().wolff_set_lds_slab(self._h, int(slab_bits)), "wolff_set_lds_slab")
 
     def set_graph(self, chunk: int):
         _check(load().wolff_set_graph(self._h, int(chunk)), "wolff_set_graph")

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBRARY = os.path.join(HERE, "libwolff.so")
 SOURCES = ["wolff_lib.hip"]
-DEPENDS = ["wolff_lib.hip", "wolff_kernels.hip", "wolff_kernels.h", "wolff_device.h"]
+DEPENDS = ["wolff_lib.hip", "wolff_kernels.hip", "wolff_kernels.h", "wolff_device.h", "wolff_lds.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

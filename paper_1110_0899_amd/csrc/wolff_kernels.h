@@ -41,6 +41,7 @@ struct Rep {
     uint32_t pad_q;
     int64_t M;              // magnetisation after the last update
     int64_t B;              // bond sum (valid when b_valid)
+    const uint32_t* abort;  // host-mapped stop request, read once per update (NULL: none)
 };
 
 // Per-update control block of the team path.
@@ -57,7 +58,7 @@ struct TeamCtl {
     long long acc_diff;     // measurement: differing bonds (Potts: equal bonds)
     long long acc_neg;      // measurement: negative spins (Potts: colour-0 sites)
     uint32_t blocks_done;
-    uint32_t pad2;
+    uint32_t aborted;       // 1: the update was not started (stop request seen)
 };
 
 }  // namespace wolff

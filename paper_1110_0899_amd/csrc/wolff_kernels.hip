@@ -135,7 +135,8 @@ __device__ __forceinline__ void expand_site_wg(bool active, uint32_t j, const ui
                                                uint32_t key, uint32_t thr, uint32_t k0,
                                                uint32_t k1, uint32_t t, uint32_t s,
                                                bool won[2 * DIM], uint32_t* tab,
-                                               uint32_t& n_anti, uint32_t& n_inner)
+                                               uint32_t& n_anti, uint32_t& n_inner,
+                                               uint32_t no_inner = 0u)
 {
     uint32_t b[2 * DIM];
 #pragma unroll
@@ -149,7 +150,7 @@ __device__ __forceinline__ void expand_site_wg(bool active, uint32_t j, const ui
         const uint32_t r = (m & 1) ? rm[m / 2] : rp[m / 2];
         act[m] = active && same && r < thr;
         n_anti += (active && !same && !is_member(b[m], key)) ? 1u : 0u;
-        n_inner += (active && is_expanded(b[m], key)) ? 1u : 0u;
+        n_inner += (active && is_expanded(b[m], key) && !((no_inner >> m) & 1u)) ? 1u : 0u;
     }
     table_claims<WG, DIM>(tab, sa, act, won);
 #pragma unroll
@@ -467,30 +468,40 @@ __device__ __forceinline__ void reduce_lattice_wg(const int8_t* S, const Geo& g,
     __syncthreads();
 }
 
-// Word i of a lattice with every tag removed: each byte becomes the plain
-// +-1 that its bit 1 holds (bytes beyond N are kept).
-__device__ __forceinline__ uint32_t plain_word(uint32_t w, uint32_t i, uint32_t N)
+// A spin byte with its member tag removed: the plain +-1 that bit 1 holds.
+__device__ __forceinline__ uint32_t plain_word(uint32_t w)
 {
     const uint32_t neg = (w >> 1) & 0x01010101u;                  // 1 where the spin is -1
-    uint32_t clean = 0x01010101u | (neg * 0xFEu);
-    if (4u * i + 4u > N) {
-        const uint32_t keep = 0xFFFFFFFFu << (8u * (N - 4u * i));
-        clean = (clean & ~keep) | (w & keep);
+    return 0x01010101u | (neg * 0xFEu);
+}
+
+__device__ __forceinline__ int8_t plain_byte(int8_t b) { return (b & 2) ? (int8_t)-1 : (int8_t)1; }
+
+// Remove the member tags from lattice bytes [0, N): whole words first, then
+// the last N mod 4 bytes one by one (the lattice may be a caller's buffer of
+// exactly N bytes).  Items first, first + stride, ...
+__device__ __forceinline__ void clear_tags(int8_t* S, uint32_t N, uint32_t first, uint32_t stride)
+{
+    uint32_t* W = reinterpret_cast<uint32_t*>(S);
+    const uint32_t nw = N >> 2;
+    for (uint32_t i = first; i < nw; i += stride) {
+        const uint32_t w = W[i];
+        const uint32_t clean = plain_word(w);
+        if (clean != w) W[i] = clean;
     }
-    return clean;
+    const uint32_t k = 4u * nw + first;
+    if (first < 4u && k < N) {
+        const int8_t b = S[k];
+        const int8_t clean = plain_byte(b);
+        if (clean != b) S[k] = clean;
+    }
 }
 
 // Remove the member tags from a whole lattice, by one workgroup.
 template <int WG>
 __device__ __forceinline__ void clear_tags_wg(int8_t* S, uint32_t N)
 {
-    uint32_t* W = reinterpret_cast<uint32_t*>(S);
-    const uint32_t nw = (N + 3u) >> 2;
-    for (uint32_t i = threadIdx.x; i < nw; i += WG) {
-        const uint32_t w = W[i];
-        const uint32_t clean = plain_word(w, i, N);
-        if (clean != w) W[i] = clean;
-    }
+    clear_tags(S, N, threadIdx.x, WG);
     __syncthreads();
 }
 
@@ -501,6 +512,27 @@ __device__ __forceinline__ void clear_tags_wg(int8_t* S, uint32_t N)
 // Items are appended in whole steps: ballot/mbcnt inside each wave, a prefix
 // over the waves' counts in LDS, one store per new site.
 
+// Neighbour slots of site j (+x, -x, +y, -y[, +z, -z] as bits 0..2d-1)
+// whose bond crosses the periodic boundary, and the same for the +mu slots
+// only (the bonds that site j is the base of).
+template <int DIM>
+__device__ __forceinline__ uint32_t wrap_slots(const Geo& g, uint32_t j)
+{
+    const uint32_t L = g.L;
+    const uint32_t q = g.div_L(j);
+    const uint32_t x = j - q * L;
+    uint32_t m = (x + 1u == L ? 1u : 0u) | (x == 0u ? 2u : 0u);
+    if (DIM == 2) {
+        m |= (q + 1u == L ? 4u : 0u) | (q == 0u ? 8u : 0u);
+    } else {
+        const uint32_t z = g.div_L(q);
+        const uint32_t y = q - z * L;
+        m |= (y + 1u == L ? 4u : 0u) | (y == 0u ? 8u : 0u) | (z + 1u == L ? 16u : 0u) |
+             (z == 0u ? 32u : 0u);
+    }
+    return m;
+}
+
 // Workgroup-shared control words of the one-workgroup path.
 struct WgCtl {
     int s0;                 // seed spin (Ising) or colour (Potts) of the current update
@@ -508,6 +540,7 @@ struct WgCtl {
     uint32_t idx;           // next replica (work counter)
     int32_t cb;             // byte written to claimed sites
     uint64_t t_start;       // wall clock at the workgroup's start
+    uint32_t faces;         // odd L: expanded members listed on a last face
 };
 
 // Time budget of a launch, checked by thread 0 only and broadcast through
@@ -515,6 +548,14 @@ struct WgCtl {
 __device__ __forceinline__ uint32_t budget_spent(const WgCtl* c, uint64_t budget)
 {
     return (budget != 0u && wall_clock64() - c->t_start >= budget) ? 1u : 0u;
+}
+
+// Stop request of a lattice: a flag in host memory mapped into the device's
+// address space, set by the host while kernels run, read at system scope.
+__device__ __forceinline__ uint32_t abort_requested(const uint32_t* flag)
+{
+    return (flag != nullptr &&
+            __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) ? 1u : 0u;
 }
 
 // Up to max_updates (0: all left) updates of replica R, stopping early at an
@@ -548,10 +589,24 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
     const uint32_t pq = R->q;                                     // 0: Ising, else Potts q
     // With measurement on an even-L (bipartite) Ising lattice the bond sum
     // follows the cluster; otherwise it is recounted over the lattice per update.
-    const bool incr = measure && pq == 0u && (g.L & 1u) == 0u;
+    const bool incr = measure && pq == 0u;
+    // odd L: the lattice is not bipartite across the periodic boundary, so
+    // a bond that wraps around is left out of the expansion-time count and
+    // counted once the cluster is complete, from its member on the last face
+    const bool odd = (g.L & 1u) != 0u;
     uint32_t err = 0u;
     const uint32_t QC = qmask + 1u;
     uint32_t* tab = q + QC;                                       // claim table after the ring
+
+    // a stop request seen before the first update: run none (the state
+    // stays exact; the request is polled again after every update)
+    const uint32_t* abort_flag = R->abort;
+    if (abort_flag != nullptr) {
+        if (tid == 0) ctl->stop = abort_requested(abort_flag);
+        __syncthreads();
+        if (ctl->stop) n = 0u;
+        __syncthreads();
+    }
 
     uint32_t done = 0u;
     while (done < n) {
@@ -587,6 +642,7 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
             q[0] = s;
             ctl->s0 = s0;
             ctl->cb = cbyte;
+            ctl->faces = 0u;
         }
         __syncthreads();
         const int s0 = ctl->s0;
@@ -626,9 +682,24 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
             }
             uint32_t nb[2 * DIM], sa[2 * DIM];
             neighbours<DIM>(g, j, nb, sa);
+            uint32_t wm = 0u;                                         // odd L: slots that wrap around
+            if (incr && odd && active) wm = wrap_slots<DIM>(g, j);
             bool won[2 * DIM];
             expand_site_wg<DIM, WG>(active, j, nb, sa, SG, emask, evalue, cb, key, thr, k0, k1, t,
-                                    s, won, tab, n_anti, n_inner);
+                                    s, won, tab, n_anti, n_inner, wm);
+            if (incr && odd) {
+                // list the members on a last face (a +mu bond of theirs wraps
+                // around) below the top of the overflow stack: the stack holds
+                // unexpanded members, the list expanded ones, at most N together
+                const bool face = (wm & 0x15u) != 0u;
+                const uint64_t fm = __ballot(face);
+                if (fm) {
+                    uint32_t base = 0u;
+                    if (lane == 0) base = atomicAdd(&ctl->faces, (uint32_t)__popcll(fm));
+                    base = __shfl(base, 0, WAVE);
+                    if (face) ov[g.N - 1u - (base + lane_prefix(fm))] = j;
+                }
+            }
             uint32_t pos[2 * DIM];
             const uint32_t wtot = wave_compact<DIM>(won, pos);
             if (lane == 0) wave_cnt[wv] = wtot;
@@ -668,6 +739,24 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
         else
             M -= 2 * (int64_t)s0 * (int64_t)csize;                  // exact |dM| = 2|C|
         if (incr) {
+            if (odd) {
+                // the wrap-around bonds inside the cluster, each from its
+                // member on the last face
+                const uint32_t nf = ctl->faces;
+                for (uint32_t i = tid; i < nf; i += WG) {
+                    const uint32_t jf = ov[g.N - 1u - i];
+                    const uint32_t wf = wrap_slots<DIM>(g, jf);
+                    const uint32_t L = g.L;
+                    uint32_t kk[DIM];
+                    kk[0] = jf - (L - 1u);                            // +x of x = L - 1
+                    kk[1] = jf - (L - 1u) * L;                        // +y of y = L - 1
+                    if (DIM == 3) kk[DIM - 1] = jf - (L - 1u) * g.LL; // +z of z = L - 1
+#pragma unroll
+                    for (int mu = 0; mu < DIM; ++mu)
+                        if ((wf >> (2 * mu)) & 1u)
+                            n_inner += is_member((uint8_t)SG[site_addr<DIM>(g, kk[mu])], key) ? 1u : 0u;
+                }
+            }
             // Flipping C changes only the bonds between C and the rest: with
             // n_anti of them anti-aligned and 2d|C| - n_anti - 2 n_inner
             // aligned, dB = -4 (d |C| - n_anti - n_inner).
@@ -691,7 +780,7 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
             r.mag = M;
             r.csize = (int64_t)csize;
             rec[u] = r;
-            ctl->stop = budget_spent(ctl, budget);
+            ctl->stop = budget_spent(ctl, budget) | abort_requested(abort_flag);
         }
         __syncthreads();
         ++done;
@@ -752,17 +841,11 @@ __global__ __launch_bounds__(WG) void batch_kernel(Rep* reps, const uint32_t* or
 }
 
 // Remove the member tags from a lattice, grid-wide (before the team path,
-// which works on plain bytes, takes over a lattice).
+// which works on plain bytes, takes over a lattice, and at the end of a
+// no-allocation run on a caller's lattice).
 __global__ void plain_kernel(int8_t* S, uint32_t N)
 {
-    uint32_t* W = reinterpret_cast<uint32_t*>(S);
-    const uint32_t nw = (N + 3u) >> 2;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += stride) {
-        const uint32_t w = W[i];
-        const uint32_t clean = plain_word(w, i, N);
-        if (clean != w) W[i] = clean;
-    }
+    clear_tags(S, N, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 __global__ void reset_counter_kernel(uint32_t* c)
@@ -818,6 +901,11 @@ __global__ __launch_bounds__(WG) void measure_rep_kernel(Rep* R)
 __global__ void team_seed_kernel(Rep* R, TeamCtl* ctl, unsigned long long* gq)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (abort_requested(R->abort)) {             // stop request: leave the update undone
+        ctl->aborted = 1u;
+        return;
+    }
+    ctl->aborted = 0u;
     const Geo g = R->geo;
     const uint32_t t = R->t;
     const uint32_t s = seed_site(R->k0, R->k1, t, g.N);
@@ -858,6 +946,7 @@ __global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned
     __shared__ uint32_t sh_take[3];   // first slot, count, done flag
     __shared__ uint32_t sh_push;
 
+    if (ctl->aborted) return;                    // the seed kernel saw a stop request
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (WAVE - 1);
     const uint32_t wv = tid / WAVE;
@@ -1018,6 +1107,7 @@ __global__ __launch_bounds__(256) void measure_grid_kernel(Rep* R, TeamCtl* ctl)
 {
     constexpr int WG = 256, NW = WG / WAVE;
     __shared__ long long red[2 * NW];
+    if (ctl->aborted) return;
     const Geo g = R->geo;
     const uint32_t pq = R->q;
     uint64_t d, neg;

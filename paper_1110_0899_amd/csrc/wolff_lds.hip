@@ -1,0 +1,677 @@
+// LDS-resident growth path of the Wolff update (Section 2, steps (i)-(v);
+// the cluster grown frontier-parallel as in Section 4, step (iii')).
+//
+// The lattice of an Ising run lives in the LDS of a team of G workgroups
+// for a whole launch, one bit per spin: workgroup g holds slab g, a range of
+// whole rows (2D) or whole planes (3D).  Neighbour gathers and claims are LDS
+// reads and LDS atomics; only a bond that leaves the slab goes through
+// global memory, as a message to the slab that owns the far site.  With
+// G = 1 (a lattice that fits one workgroup's LDS) nothing leaves the
+// workgroup at all.
+//
+// Layout of a slab: rows of Lp = 32 * ceil(L / 32) bits, row r of the
+// lattice (r = y in 2D, r = z L + y in 3D) at bit (r - r0) Lp of its slab,
+// site x of a row at bit x; bit 1 = spin -1.  A site is named by its logical
+// index j = x + L r, as everywhere else (random-stream counters, messages,
+// records).
+//
+// Per update t, every workgroup draws the seed site s; its owner claims it
+// (the claim flips the bit) and starts the frontier.  A workgroup expands
+// sites from an LDS ring (spilling to a private global stack), claims local
+// neighbours whose bond is active with an LDS atomic OR / AND that flips the
+// bit (exactly one caller sees the old bit equal to the seed spin s0), and
+// sends a message (site, s0) for every active bond whose far site is in
+// another slab; the receiver claims it if its spin is s0.  A device-scope
+// counter P = (t + 1) << 32 | outstanding units (claimed sites not yet
+// expanded plus messages not yet consumed) decides when the cluster is
+// complete: a workgroup adds its net change once per step, and a step that
+// sends messages waits for its addition to be performed before the messages
+// become visible, so P never reaches 0 while work is left.  After P reaches
+// 0 the team counts the bond sum (every slab its rows plus the rows it
+// shares with the next slab, whose first row each slab publishes) and its
+// negative spins, and the last workgroup at the update's grid barrier writes
+// the record.  The barrier also orders the updates: no workgroup starts
+// update t + 1 before all have finished update t.
+#pragma once
+
+#include "wolff_kernels.h"
+
+namespace wolff {
+
+// Geometry of the bit lattice and its slabs (host-computed).
+struct LdsGeo {
+    uint32_t L;
+    uint32_t N;             // L^dim
+    uint32_t Lp;            // bits per row (L rounded up to 32)
+    uint32_t RW;            // words per row
+    uint32_t rows;          // rows of the lattice: L (2D), L * L (3D)
+    uint32_t slab_rows;     // rows per slab (3D: a multiple of L)
+    uint32_t slab_words;    // slab_rows * RW
+    uint32_t G;             // slabs (workgroups)
+    Div dL;                 // division by L
+    Div dslab;              // division of a row index by slab_rows
+};
+
+// Team state in device memory (zeroed once when the lattice first takes
+// this path; every field is back to its idle value at the end of a launch).
+struct LdsCtl {
+    unsigned long long P;          // (epoch << 32) | outstanding units; epoch = t + 1
+    uint32_t bar_count;            // grid barrier: arrivals
+    uint32_t bar_gen;              // grid barrier: generation
+    unsigned long long acc_diff;   // this update: differing bonds
+    unsigned long long acc_neg;    // this update: negative spins
+    unsigned long long acc_claims; // this update: sites claimed (|C|)
+    unsigned long long acc_dm;     // this update: change of the magnetisation (two's complement)
+    int64_t M;                     // magnetisation after the last update
+    int64_t B;                     // bond sum after the last measured update
+    uint32_t stop;                 // 1: stop before the next update (stop request)
+    uint32_t err;                  // ERR_* bits seen by any workgroup
+    uint32_t done;                 // updates completed in this launch
+    uint32_t pad;
+};
+
+struct LdsArgs {
+    Rep* R;
+    LdsCtl* ctl;
+    unsigned long long* inbox;     // G rings of imask + 1 entries
+    uint32_t* inbox_tail;          // G counters (slots reserved so far)
+    uint32_t imask;
+    uint32_t* bnd;                 // G * bnd_words: first row (2D) / plane (3D) of every slab
+    uint32_t bnd_words;
+    uint32_t* ov;                  // G private overflow stacks of ov_stride entries
+    uint32_t ov_stride;
+    uint32_t qmask;                // LDS ring entries - 1
+    LdsGeo lg;
+};
+
+constexpr uint32_t MSG_S0_NEG = 0x80000000u;   // message word: seed spin -1
+// Bound on the polls of one wait (a poll is ~0.3 to 1 us: seconds in all,
+// far above any legitimate wait).  A wait past it flags ERR_TEAM_WAIT and
+// the stop request, so the launch ends at the next update boundary.
+constexpr uint32_t LDS_SPIN_LIMIT = 1u << 22;
+
+__device__ __forceinline__ void flag_wait_failure(LdsCtl* ctl);
+
+__device__ __forceinline__ uint64_t ld_agent(const unsigned long long* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void flag_wait_failure(LdsCtl* ctl)
+{
+    __hip_atomic_fetch_or(&ctl->err, ERR_TEAM_WAIT, __ATOMIC_RELAXED, SCOPE_AGENT);
+    __hip_atomic_store(&ctl->stop, 1u, __ATOMIC_RELAXED, SCOPE_AGENT);
+}
+
+// Grid barrier of the G workgroups of a launch (all co-resident).  Thread 0
+// arrives; the last arrival runs `last()` (with every other workgroup's
+// earlier writes visible) before it opens the barrier.  A wait past its
+// bound sets ERR_TEAM_WAIT and leaves.
+template <typename F>
+__device__ __forceinline__ void grid_barrier(LdsCtl* ctl, uint32_t G, F last)
+{
+    if (threadIdx.x == 0) {
+        if (G == 1) {
+            last();
+        } else {
+            const uint32_t gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, SCOPE_AGENT);
+            const uint32_t prev = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL, SCOPE_AGENT);
+            if (prev == G - 1u) {
+                last();
+                __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, SCOPE_AGENT);
+                __hip_atomic_store(&ctl->bar_gen, gen + 1u, __ATOMIC_RELEASE, SCOPE_AGENT);
+            } else {
+                uint32_t polls = 0u;
+                while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, SCOPE_AGENT) == gen) {
+                    if (++polls > LDS_SPIN_LIMIT) {
+                        flag_wait_failure(ctl);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Bit address of site (x, row r) inside its slab (r0 = first row of the slab).
+__device__ __forceinline__ uint32_t slab_bit(const LdsGeo& lg, uint32_t x, uint32_t r, uint32_t r0)
+{
+    return (r - r0) * lg.Lp + x;
+}
+
+__device__ __forceinline__ uint32_t bit_of(const uint32_t* bits, uint32_t a)
+{
+    return (bits[a >> 5] >> (a & 31u)) & 1u;
+}
+
+// Claim local bit a for a cluster of seed bit b0 (0: spin +1, 1: spin -1):
+// flip it to !b0 with one LDS atomic; true for the one caller that found b0.
+__device__ __forceinline__ bool claim_bit(uint32_t* bits, uint32_t a, uint32_t b0)
+{
+    const uint32_t m = 1u << (a & 31u);
+    if (b0 == 0u) return (atomicOr(&bits[a >> 5], m) & m) == 0u;
+    return (atomicAnd(&bits[a >> 5], ~m) & m) != 0u;
+}
+
+// Count differing bonds and negative spins of the slab's rows: the +x bond
+// of every site, the +y bond (2D: to the next row, 3D: within the plane),
+// and the +z bond (3D: to the next plane).  A bond to the next slab's first
+// row / plane reads it from global memory, where that slab published it
+// (G = 1 never does: every row is its own).  Items: words of the slab,
+// thread-strided.
+template <int WG, int DIM>
+__device__ __forceinline__ void slab_counts(const uint32_t* bits, const LdsGeo& lg, uint32_t g,
+                                            const uint32_t* next_first_global, uint64_t& ndiff,
+                                            uint64_t& nneg)
+{
+    const uint32_t r0 = g * lg.slab_rows;
+    const uint32_t nrows = min(lg.slab_rows, lg.rows - r0);
+    const uint32_t RW = lg.RW, L = lg.L;
+    const uint32_t tail_bits = L - (RW - 1u) * 32u;                  // valid bits of a row's last word
+    const uint32_t tail_mask = tail_bits == 32u ? 0xFFFFFFFFu : ((1u << tail_bits) - 1u);
+    uint64_t d = 0u, neg = 0u;
+    for (uint32_t w = threadIdx.x; w < nrows * RW; w += WG) {
+        const uint32_t lr = w / RW;
+        const uint32_t wi = w - lr * RW;
+        const uint32_t v = bits[w];
+        const bool last_word = wi == RW - 1u;
+        const uint32_t valid = last_word ? tail_mask : 0xFFFFFFFFu;
+        neg += __popc(v & valid);
+        // +x: bit i against bit i + 1 of the row (bit L - 1 against bit 0)
+        uint32_t nx;
+        if (!last_word) {
+            nx = (v >> 1) | (bits[w + 1u] << 31);
+        } else {
+            const uint32_t first = bits[w - wi] & 1u;
+            nx = (v >> 1) | (first << (tail_bits - 1u));
+            if (tail_bits == 32u) nx = (v >> 1) | (first << 31);
+        }
+        d += __popc((v ^ nx) & valid);
+        // +y / +z neighbours: row words
+        const uint32_t r = r0 + lr;
+        if (DIM == 2) {
+            const uint32_t ry = (r + 1u == lg.rows) ? 0u : r + 1u;  // row of the +y neighbours
+            const uint32_t vy = (ry >= r0 && ry < r0 + nrows) ? bits[(ry - r0) * RW + wi]
+                                                              : ld_agent(&next_first_global[wi]);   // the next slab's first row
+            d += __popc((v ^ vy) & valid);
+        } else {
+            const uint32_t z = lg.dL.div(r);
+            const uint32_t y = r - z * L;
+            const uint32_t ry = (y + 1u == L) ? r + 1u - L : r + 1u;   // +y: within the plane
+            d += __popc((v ^ bits[(ry - r0) * RW + wi]) & valid);
+            const uint32_t rz = (r + L >= lg.rows) ? r + L - lg.rows : r + L;
+            const uint32_t vz = (rz >= r0 && rz < r0 + nrows) ? bits[(rz - r0) * RW + wi]
+                                                              : ld_agent(&next_first_global[y * RW + wi]);  // row y of the next slab's first plane
+            d += __popc((v ^ vz) & valid);
+        }
+    }
+    ndiff = d;
+    nneg = neg;
+}
+
+template <int WG, int DIM>
+__global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates)
+{
+    constexpr int NW = WG / WAVE;
+    extern __shared__ __align__(16) uint32_t lds[];
+    __shared__ uint32_t wave_cnt[NW];
+    __shared__ uint32_t wave_snd[2 * NW];
+    __shared__ uint64_t red[2 * NW];
+    __shared__ uint32_t sh[8];
+
+    const LdsGeo lg = a.lg;
+    uint32_t* bits = lds;
+    uint32_t* q = lds + ((lg.slab_words + 3u) & ~3u);
+    const uint32_t QC = a.qmask + 1u;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (WAVE - 1);
+    const uint32_t wv = tid / WAVE;
+    const uint32_t g = blockIdx.x;
+    const uint32_t G = lg.G;
+    const uint32_t r0 = g * lg.slab_rows;
+    const uint32_t nrows = min(lg.slab_rows, lg.rows - r0);
+    const uint32_t L = lg.L;
+    Rep* R = a.R;
+    LdsCtl* ctl = a.ctl;
+    const Geo geo = R->geo;
+    const uint32_t thr = R->thr, k0 = R->k0, k1 = R->k1;
+    const uint32_t t0 = R->t;
+    uint32_t n = R->n_left;
+    if (max_updates != 0u && max_updates < n) n = max_updates;
+    const bool measure = R->measure != 0u;
+    const uint32_t gprev = (g == 0u) ? G - 1u : g - 1u;
+    const uint32_t gnext = (g + 1u == G) ? 0u : g + 1u;
+    gword* ov = as_global(a.ov + (size_t)g * a.ov_stride);
+    unsigned long long* inbox = a.inbox + (size_t)g * (a.imask + 1u);
+    const gbyte* SG = as_global(R->S);
+
+    // the slab from the int8 lattice (any storage order; bit 1 of a byte is
+    // its sign, member tags included)
+    for (uint32_t w = tid; w < nrows * lg.RW; w += WG) {
+        const uint32_t lr = w / lg.RW;
+        const uint32_t x0 = (w - lr * lg.RW) * 32u;
+        const uint32_t base = (r0 + lr) * L;
+        uint32_t v = 0u;
+        for (uint32_t b = 0; b < 32u && x0 + b < L; ++b) {
+            const uint32_t j = base + x0 + b;
+            const uint32_t addr = (DIM == 2) ? site_addr<2>(geo, j) : site_addr<3>(geo, j);
+            v |= (((uint32_t)(uint8_t)SG[addr] >> 1) & 1u) << b;
+        }
+        bits[w] = v;
+    }
+    uint32_t ihead = 0u;
+    if (tid == 0) {
+        ihead = G > 1u ? ld_agent(&a.inbox_tail[g]) : 0u;     // every message was consumed
+        sh[0] = ihead;
+        sh[3] = ihead;
+    }
+    // a stop request seen before the first update: run none
+    grid_barrier(ctl, G, [&] {
+        __hip_atomic_store(&ctl->stop, abort_requested(R->abort), __ATOMIC_RELAXED, SCOPE_AGENT);
+        __hip_atomic_store(&ctl->P, (unsigned long long)t0 << 32, __ATOMIC_RELAXED, SCOPE_AGENT);
+        ctl->M = R->M;
+        ctl->B = R->B;
+        ctl->acc_diff = ctl->acc_neg = ctl->acc_claims = 0ull;
+        ctl->acc_dm = 0ull;
+    });
+    if (tid == 0) sh[5] = __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, SCOPE_AGENT);
+    __syncthreads();
+    ihead = sh[0];
+    if (sh[5]) n = 0u;
+    const uint64_t rec0 = R->rec_count;
+    __syncthreads();
+
+    uint32_t done = 0u;
+    for (; done < n; ++done) {
+        const uint32_t t = t0 + done;
+        const unsigned long long epoch = (unsigned long long)(t + 1u) << 32;
+        const uint32_t s = seed_site(k0, k1, t, lg.N);                // step (i)
+        const uint32_t srow = lg.dL.div(s);
+        const uint32_t owner = lg.dslab.div(srow);
+        uint32_t head = 0u, tail = 0u, ovn = 0u;
+        uint32_t claims = 0u, nstep = 0u;
+        if (g == owner) {
+            if (tid == 0) {
+                const uint32_t a0 = slab_bit(lg, s - srow * L, srow, r0);
+                const uint32_t b0 = bit_of(bits, a0);
+                claim_bit(bits, a0, b0);
+                q[0] = s;
+                sh[1] = b0;
+                sh[2] = 1u;                                       // s0 known
+                if (G > 1u)
+                    __hip_atomic_store(&ctl->P, epoch | 1ull, __ATOMIC_RELAXED, SCOPE_AGENT);
+            }
+            tail = 1u;
+            claims = 1u;
+        } else if (tid == 0) {
+            sh[2] = 0u;                                           // s0 not known yet
+        }
+        __syncthreads();
+
+        while (true) {
+            uint32_t avail = tail - head;
+            if (avail < (uint32_t)WG && ovn > 0u) {                 // refill the ring
+                const uint32_t m = min(ovn, QC - avail);
+                for (uint32_t i = tid; i < m; i += WG) q[(tail + i) & a.qmask] = ov[ovn - m + i];
+                tail += m;
+                ovn -= m;
+                __syncthreads();
+                avail = tail - head;
+            }
+            // messages from the other slabs: while the workgroup has work of
+            // its own it looks at its inbox through the tail read (without
+            // waiting) during every fourth step; idle, it polls the inbox and P
+            uint32_t itail = ihead;
+            if (G > 1u) {
+                if (avail == 0u) {
+                    if (tid == 0) {
+                        uint32_t it = ld_agent(&a.inbox_tail[g]);
+                        uint32_t fin = 0u;
+                        uint32_t polls = 0u, backoff = 1u;
+                        while (it == ihead) {
+                            const unsigned long long p = ld_agent(&ctl->P);
+                            if ((p >> 32) > (epoch >> 32) || p == epoch) {
+                                // P reached 0: every message was consumed
+                                it = ld_agent(&a.inbox_tail[g]);
+                                fin = it == ihead ? 1u : 0u;
+                                break;
+                            }
+                            if (++polls > LDS_SPIN_LIMIT ||
+                                __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, SCOPE_AGENT)) {
+                                if (polls > LDS_SPIN_LIMIT) flag_wait_failure(ctl);
+                                fin = 1u;
+                                break;
+                            }
+                            for (uint32_t b = 0; b < backoff; ++b) __builtin_amdgcn_s_sleep(1);
+                            if (backoff < 8u) backoff <<= 1;
+                            it = ld_agent(&a.inbox_tail[g]);
+                        }
+                        sh[3] = it;
+                        sh[4] = fin;
+                    }
+                    __syncthreads();
+                    const uint32_t fin = sh[4];
+                    itail = sh[3];
+                    __syncthreads();
+                    if (fin) break;
+                } else {
+                    itail = sh[3];                                // the latest tail read (may lag)
+                }
+            } else if (avail == 0u) {
+                break;                                            // one workgroup: the cluster is complete
+            }
+
+            if (itail != ihead) {
+                // claim the sites of up to WG messages (the sender found the bond active)
+                const uint32_t m = min(itail - ihead, (uint32_t)WG);
+                bool won = false;
+                uint32_t k = 0u;
+                if (tid < m) {
+                    const unsigned long long* slot = &inbox[(ihead + tid) & a.imask];
+                    unsigned long long v = ld_agent(slot);
+                    uint32_t polls = 0u;
+                    while ((v >> 32) != (epoch >> 32)) {          // reserved, not yet written
+                        if (++polls > LDS_SPIN_LIMIT) {
+                            flag_wait_failure(ctl);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                        v = ld_agent(slot);
+                    }
+                    if ((v >> 32) == (epoch >> 32)) {
+                        const uint32_t w = (uint32_t)v;
+                        k = w & ~MSG_S0_NEG;
+                        const uint32_t b0 = (w & MSG_S0_NEG) ? 1u : 0u;
+                        sh[1] = b0;                               // every message carries s0
+                        const uint32_t kr = lg.dL.div(k);
+                        won = claim_bit(bits, slab_bit(lg, k - kr * L, kr, r0), b0);
+                    }
+                }
+                const uint64_t mask = __ballot(won);
+                const uint32_t pos = lane_prefix(mask);
+                if (lane == 0) wave_cnt[wv] = (uint32_t)__popcll(mask);
+                __syncthreads();
+                uint32_t before = 0u, total = 0u;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    const uint32_t c = wave_cnt[w];
+                    before += ((uint32_t)w < wv) ? c : 0u;
+                    total += c;
+                }
+                if (total <= QC - (tail - head)) {
+                    if (won) q[(tail + before + pos) & a.qmask] = k;
+                    tail += total;
+                } else {
+                    if (won) ov[ovn + before + pos] = k;
+                    ovn += total;
+                }
+                claims += total;
+                ihead += m;
+                if (tid == 0) {
+                    sh[2] = 1u;
+                    const long long delta = (long long)total - (long long)m;
+                    if (delta != 0)
+                        __hip_atomic_fetch_add(&ctl->P, (unsigned long long)delta, __ATOMIC_RELAXED, SCOPE_AGENT);
+                }
+                __syncthreads();
+                continue;
+            }
+            if (avail == 0u) continue;                            // (G > 1) poll again
+
+            // ---- one growth step over up to WG frontier sites (steps (ii)-(iii))
+            const uint32_t b0 = sh[1];
+            const uint32_t nproc = min(avail, (uint32_t)WG);
+            const bool active = tid < nproc;
+            const uint32_t j = active ? q[(head + tid) & a.qmask] : 0u;
+            head += nproc;
+            const bool look = G > 1u && (nstep++ & 3u) == 0u;
+            uint32_t it_async = 0u;
+            if (look && tid == 0) it_async = ld_agent(&a.inbox_tail[g]);   // used at the end of the step
+            // coordinates and neighbours (logical indices nb, rows nr, columns nx)
+            const uint32_t r = lg.dL.div(j);
+            const uint32_t x = j - r * L;
+            uint32_t nb[2 * DIM], nr[2 * DIM], ncol[2 * DIM];
+            const uint32_t xp = (x + 1u == L) ? 0u : x + 1u;
+            const uint32_t xm = (x == 0u) ? L - 1u : x - 1u;
+            nr[0] = r; ncol[0] = xp;
+            nr[1] = r; ncol[1] = xm;
+            if (DIM == 2) {
+                nr[2] = (r + 1u == L) ? 0u : r + 1u;
+                nr[3] = (r == 0u) ? L - 1u : r - 1u;
+                ncol[2] = ncol[3] = x;
+            } else {
+                const uint32_t z = lg.dL.div(r);
+                const uint32_t y = r - z * L;
+                nr[2] = (y + 1u == L) ? r + 1u - L : r + 1u;
+                nr[3] = (y == 0u) ? r + L - 1u : r - 1u;
+                nr[4] = (z + 1u == L) ? y : r + L;
+                nr[5] = (z == 0u) ? r + lg.rows - L : r - L;
+                ncol[2] = ncol[3] = ncol[4] = ncol[5] = x;
+            }
+            bool local[2 * DIM], elig[2 * DIM];
+            uint32_t ba[2 * DIM];
+#pragma unroll
+            for (int m = 0; m < 2 * DIM; ++m) {
+                nb[m] = ncol[m] + nr[m] * L;
+                local[m] = nr[m] >= r0 && nr[m] < r0 + nrows;
+                ba[m] = local[m] ? slab_bit(lg, ncol[m], nr[m], r0) : 0u;
+                // a local neighbour is a candidate only if its spin is s0; a
+                // remote one is decided by its owner
+                elig[m] = active && (!local[m] || bit_of(bits, ba[m]) == b0);
+            }
+            // bond words, drawn only where a lane of the wave needs them: one
+            // block keyed by j for the +mu bonds, one keyed by j - e_mu per -mu bond
+            uint32_t rp[3] = {0u, 0u, 0u}, rm[3] = {0u, 0u, 0u};
+            if (elig[0] || elig[2] || (DIM == 3 && elig[2 * DIM - 2])) {
+                const U4 w4 = philox(j, t, s, DOMAIN_BOND, k0, k1);
+                rp[0] = w4.x;
+                rp[1] = w4.y;
+                rp[2] = w4.z;
+            }
+#pragma unroll
+            for (int mu = 0; mu < DIM; ++mu) {
+                if (elig[2 * mu + 1]) {
+                    const U4 w4 = philox(nb[2 * mu + 1], t, s, DOMAIN_BOND, k0, k1);
+                    rm[mu] = (mu == 0) ? w4.x : (mu == 1) ? w4.y : w4.z;
+                }
+            }
+            bool won[2 * DIM], snd[2 * DIM];
+#pragma unroll
+            for (int m = 0; m < 2 * DIM; ++m) {
+                const uint32_t rr = (m & 1) ? rm[m / 2] : rp[m / 2];
+                const bool act = elig[m] && rr < thr;
+                won[m] = act && local[m] && claim_bit(bits, ba[m], b0);
+                snd[m] = act && !local[m];
+            }
+            // compaction: claimed sites, and messages to the previous / next slab
+            uint32_t pos[2 * DIM], spos[2 * DIM];
+            const uint32_t wtot = wave_compact<DIM>(won, pos);
+            uint32_t sprev = 0u, snext = 0u;
+#pragma unroll
+            for (int m = 0; m < 2 * DIM; ++m) {
+                // the slab of a remote neighbour: +y / +z go to the next slab, -y / -z to the previous
+                const bool to_next = (m & 1) == 0;
+                const uint64_t mp = __ballot(snd[m] && !to_next);
+                const uint64_t mn = __ballot(snd[m] && to_next);
+                spos[m] = to_next ? snext + lane_prefix(mn) : sprev + lane_prefix(mp);
+                sprev += (uint32_t)__popcll(mp);
+                snext += (uint32_t)__popcll(mn);
+            }
+            if (lane == 0) {
+                wave_cnt[wv] = wtot;
+                wave_snd[wv] = sprev;
+                wave_snd[NW + wv] = snext;
+            }
+            __syncthreads();
+            uint32_t before = 0u, total = 0u, pb = 0u, ptot = 0u, nbf = 0u, ntot = 0u;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const uint32_t c = wave_cnt[w], cp = wave_snd[w], cn = wave_snd[NW + w];
+                const bool lower = (uint32_t)w < wv;
+                before += lower ? c : 0u;
+                pb += lower ? cp : 0u;
+                nbf += lower ? cn : 0u;
+                total += c;
+                ptot += cp;
+                ntot += cn;
+            }
+            if (G > 1u) {
+                if (tid == 0) {
+                    const long long delta = (long long)total + (long long)(ptot + ntot) - (long long)nproc;
+                    if (ptot + ntot > 0u) {
+                        // the units of the messages must be in P before a
+                        // receiver can consume them: wait for the addition
+                        sh[7] = (uint32_t)__hip_atomic_fetch_add(&ctl->P, (unsigned long long)delta,
+                                                                 __ATOMIC_RELAXED, SCOPE_AGENT);
+                        sh[5] = ptot ? __hip_atomic_fetch_add(&a.inbox_tail[gprev], ptot, __ATOMIC_RELAXED, SCOPE_AGENT) : 0u;
+                        sh[6] = ntot ? __hip_atomic_fetch_add(&a.inbox_tail[gnext], ntot, __ATOMIC_RELAXED, SCOPE_AGENT) : 0u;
+                    } else if (delta != 0) {
+                        __hip_atomic_fetch_add(&ctl->P, (unsigned long long)delta, __ATOMIC_RELAXED, SCOPE_AGENT);
+                    }
+                }
+                if (ptot + ntot > 0u) {
+                    __syncthreads();
+                    const uint32_t basep = sh[5], basen = sh[6];
+                    const unsigned long long word = epoch | (b0 ? MSG_S0_NEG : 0u);
+#pragma unroll
+                    for (int m = 0; m < 2 * DIM; ++m) {
+                        if (snd[m]) {
+                            const bool to_next = (m & 1) == 0;
+                            const uint32_t dst = to_next ? gnext : gprev;
+                            const uint32_t slot = to_next ? basen + nbf + spos[m] : basep + pb + spos[m];
+                            __hip_atomic_store(&a.inbox[(size_t)dst * (a.imask + 1u) + (slot & a.imask)],
+                                               word | nb[m], __ATOMIC_RELAXED, SCOPE_AGENT);
+                        }
+                    }
+                }
+            }
+            // append the claimed sites to the ring (or the overflow stack)
+            if (total <= QC - (tail - head)) {
+#pragma unroll
+                for (int m = 0; m < 2 * DIM; ++m)
+                    if (won[m]) q[(tail + before + pos[m]) & a.qmask] = nb[m];
+                tail += total;
+            } else {
+#pragma unroll
+                for (int m = 0; m < 2 * DIM; ++m)
+                    if (won[m]) ov[ovn + before + pos[m]] = nb[m];
+                ovn += total;
+            }
+            claims += total;
+            if (look && tid == 0) sh[3] = it_async;
+            __syncthreads();
+        }
+
+        // ---- step (v): the record of update t
+        const uint32_t b0 = sh[1];
+        uint64_t ndiff = 0u, nneg = 0u;
+        if (measure) {
+            if (G > 1u) {
+                // publish the first row / plane for the previous slab's count
+                const uint32_t nb_words = (DIM == 2 ? 1u : L) * lg.RW;
+                for (uint32_t w = tid; w < nb_words; w += WG)
+                    __hip_atomic_store(&a.bnd[(size_t)g * a.bnd_words + w], bits[w], __ATOMIC_RELAXED, SCOPE_AGENT);
+                grid_barrier(ctl, G, [] {});
+            }
+            slab_counts<WG, DIM>(bits, lg, g, a.bnd + (size_t)gnext * a.bnd_words, ndiff, nneg);
+        }
+        uint64_t dsum = wave_sum_u64(ndiff), nsum = wave_sum_u64(nneg);
+        if (lane == 0) {
+            red[wv] = dsum;
+            red[NW + wv] = nsum;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint64_t sd = 0u, sn = 0u;
+            for (int w = 0; w < NW; ++w) {
+                sd += red[w];
+                sn += red[NW + w];
+            }
+            if (G > 1u) {
+                if (measure) {
+                    __hip_atomic_fetch_add(&ctl->acc_diff, (unsigned long long)sd, __ATOMIC_RELAXED, SCOPE_AGENT);
+                    __hip_atomic_fetch_add(&ctl->acc_neg, (unsigned long long)sn, __ATOMIC_RELAXED, SCOPE_AGENT);
+                }
+                if (claims) {
+                    // a slab that claimed sites knows s0: M changes by -2 s0 per claim
+                    const long long dm = (b0 ? 2ll : -2ll) * (long long)claims;
+                    __hip_atomic_fetch_add(&ctl->acc_claims, (unsigned long long)claims, __ATOMIC_RELAXED, SCOPE_AGENT);
+                    __hip_atomic_fetch_add(&ctl->acc_dm, (unsigned long long)dm, __ATOMIC_RELAXED, SCOPE_AGENT);
+                }
+            } else {
+                ctl->acc_diff = sd;
+                ctl->acc_neg = sn;
+                ctl->acc_claims = claims;
+                ctl->acc_dm = (unsigned long long)((b0 ? 2ll : -2ll) * (long long)claims);
+            }
+        }
+        grid_barrier(ctl, G, [&] {
+            // the last workgroup: |C|, M exactly (M -= 2 s0 |C|, summed over
+            // the slabs that claimed), B and the M recount, the record, and
+            // the stop request
+            const unsigned long long csize = ld_agent(&ctl->acc_claims);
+            const int64_t M = ctl->M + (int64_t)ld_agent(&ctl->acc_dm);
+            int64_t B = ctl->B;
+            if (measure) {
+                B = (int64_t)DIM * (int64_t)lg.N - 2 * (int64_t)ld_agent(&ctl->acc_diff);
+                const int64_t Mm = (int64_t)lg.N - 2 * (int64_t)ld_agent(&ctl->acc_neg);
+                if (Mm != M) ctl->err |= ERR_MAG;
+            }
+            ctl->M = M;
+            ctl->B = B;
+            wolff_record rr;
+            rr.bond_sum = measure ? B : (int64_t)WOLFF_NOT_MEASURED;
+            rr.mag = M;
+            rr.csize = (int64_t)csize;
+            R->rec[rec0 + done] = rr;
+            __hip_atomic_store(&ctl->acc_diff, 0ull, __ATOMIC_RELAXED, SCOPE_AGENT);
+            __hip_atomic_store(&ctl->acc_neg, 0ull, __ATOMIC_RELAXED, SCOPE_AGENT);
+            __hip_atomic_store(&ctl->acc_claims, 0ull, __ATOMIC_RELAXED, SCOPE_AGENT);
+            __hip_atomic_store(&ctl->acc_dm, 0ull, __ATOMIC_RELAXED, SCOPE_AGENT);
+            const uint32_t failed = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, SCOPE_AGENT) != 0u;
+            __hip_atomic_store(&ctl->stop, abort_requested(R->abort) | (failed ? 1u : 0u),
+                               __ATOMIC_RELAXED, SCOPE_AGENT);
+        });
+        if (tid == 0) sh[5] = __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t stop = sh[5];
+        __syncthreads();
+        if (stop) {
+            ++done;
+            break;
+        }
+    }
+
+    // the slab back to the int8 lattice: plain +-1 bytes
+    gbyte* SW = as_global(R->S);
+    for (uint32_t w = tid; w < nrows * lg.RW; w += WG) {
+        const uint32_t lr = w / lg.RW;
+        const uint32_t x0 = (w - lr * lg.RW) * 32u;
+        const uint32_t base = (r0 + lr) * L;
+        const uint32_t v = bits[w];
+        for (uint32_t b = 0; b < 32u && x0 + b < L; ++b) {
+            const uint32_t j = base + x0 + b;
+            const uint32_t addr = (DIM == 2) ? site_addr<2>(geo, j) : site_addr<3>(geo, j);
+            SW[addr] = ((v >> b) & 1u) ? (int8_t)-1 : (int8_t)1;
+        }
+    }
+    grid_barrier(ctl, G, [&] {
+        R->t = t0 + done;
+        R->n_left -= done;
+        R->rec_count = rec0 + done;
+        R->M = ctl->M;
+        R->B = ctl->B;
+        if (done > 0u) R->b_valid = measure ? 1u : 0u;
+        R->t_norm = t0 + done;
+        R->err |= __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, SCOPE_AGENT);
+        __hip_atomic_store(&ctl->err, 0u, __ATOMIC_RELAXED, SCOPE_AGENT);
+    });
+}
+
+}  // namespace wolff

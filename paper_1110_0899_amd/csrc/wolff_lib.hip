@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "wolff_kernels.hip"
+#include "wolff_lds.hip"
 
 using wolff::Geo;
 using wolff::Rep;
@@ -59,6 +60,7 @@ extern "C" const char* wolff_strerror(int code)
     case WOLFF_EDEVICE: return "HIP runtime error";
     case WOLFF_ERANGE: return "update index out of range";
     case WOLFF_ESTATE: return "device consistency check failed";
+    case WOLFF_EABORTED: return "stopped on request";
     default: return "unknown error";
     }
 }
@@ -127,6 +129,18 @@ static Geo make_geo(int dim, uint32_t L)
     }
     g.dntx = make_div(g.ntx);
     g.dnty = make_div(g.nty);
+    return g;
+}
+
+// Geometry of a lattice stored in site order (no tiles), for lattices in a
+// caller's buffer.
+static Geo make_site_order_geo(int dim, uint32_t L)
+{
+    Geo g = make_geo(dim, L);
+    g.tiled = 0u;
+    g.ntx = g.nty = g.ntz = 1u;
+    g.dntx = make_div(1u);
+    g.dnty = make_div(1u);
     return g;
 }
 
@@ -284,6 +298,15 @@ struct wolff_sim {
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
 
+    // caller-owned device buffers (wolff_create_ex): the library frees none
+    // of S, ov, d_rec, and gq when the caller supplied it
+    bool ext_buffers = false;
+    bool ext_queue = false;
+    // stop request: a word of pinned host memory mapped into the device's
+    // address space (abort_host on the host side, abort_dev on the device side)
+    uint32_t* abort_host = nullptr;
+    uint32_t* abort_dev = nullptr;
+
     int8_t* S = nullptr;
     uint32_t* ov = nullptr;
     unsigned long long* gq = nullptr;
@@ -305,6 +328,16 @@ struct wolff_sim {
     int single_wg = 256;
     int single_q = 2048;
 
+    // LDS-resident path: team state, inboxes, boundary rows, overflow stacks
+    // (allocated on the first run on this path)
+    wolff::LdsCtl* lctl = nullptr;
+    unsigned long long* linbox = nullptr;
+    uint32_t* ltail = nullptr;
+    uint32_t* lbnd = nullptr;
+    uint32_t* lov = nullptr;
+    size_t lbytes_inbox = 0, lbytes_tail = 0;
+    uint32_t lds_slab_bits = 1u << 20;    // most spins of one workgroup's slab
+
     int graph_chunk = 16;                 // updates per captured graph (0 = no graphs)
     hipGraphExec_t graph = nullptr;       // team-path chunk of graph_chunk updates
     int graph_key[3] = {-1, -1, -1};      // (chunk, measure, team size) it was captured with
@@ -323,7 +356,7 @@ struct wolff_sim {
 // team path it is the whole cost; one workgroup takes about half as long
 // per level but also adds only ~250 (2D) or ~200 (3D) sites per
 // microsecond, and pays for its lattice recount (every 32 measured updates
-// with the incremental bond sum, Ising on even L; every measured update
+// with the incremental bond sum (Ising); every measured update
 // otherwise).  The constants are fits to MI355X timings of both paths, at
 // their default tiles, at the critical points (square lattices
 // L = 512 ... 4096, simple-cubic L = 64 ... 256, mean clusters from 4e3 to
@@ -338,7 +371,7 @@ static double single_cost_us(const wolff_sim* s)
 {
     double recount = 0.0;
     if (s->measure) {
-        const bool incremental = !s->q && s->L % 2 == 0;
+        const bool incremental = !s->q;
         recount = incremental ? (double)s->N / (32.0 * 5000.0)
                               : (double)s->N / (s->dim == 2 ? 11000.0 : 6000.0);
     }
@@ -349,6 +382,79 @@ static double single_cost_us(const wolff_sim* s)
 static double team_cost_us(const wolff_sim* s)
 {
     return 15.0 + depth_us(s->dim, s->csize_mean) + (s->measure ? 8.0 + (double)s->N / 1e6 : 0.0);
+}
+
+// ----------------------------------------------------- LDS-resident path
+// Slabs of at most LDS_SLAB_BITS bits (128 KiB) per workgroup, whole rows
+// (2D) or whole planes (3D), as few slabs as fit; at most LDS_MAX_SLABS
+// workgroups, all resident at once.  The ring of LDS_RING entries follows
+// the slab in LDS.
+static constexpr uint32_t LDS_SLAB_BITS = 1u << 20;
+static constexpr uint32_t LDS_RING = 2048;
+static constexpr uint32_t LDS_MAX_SLABS = 64;
+
+struct LdsPlan {
+    wolff::LdsGeo lg;
+    int wg;
+    uint32_t imask;         // inbox entries - 1
+    uint32_t bnd_words;
+    uint32_t ov_stride;
+    size_t lds_bytes;
+};
+
+static bool lds_plan(int dim, uint32_t L, uint32_t slab_bits, LdsPlan* out)
+{
+    wolff::LdsGeo lg{};
+    lg.L = L;
+    lg.N = dim == 2 ? L * L : L * L * L;
+    lg.RW = (L + 31u) / 32u;
+    lg.Lp = 32u * lg.RW;
+    lg.rows = dim == 2 ? L : L * L;
+    const uint64_t unit_bits = (uint64_t)lg.Lp * (dim == 2 ? 1u : L);   // a row or a plane
+    if (unit_bits > slab_bits) return false;
+    const uint32_t per_slab = (uint32_t)std::min<uint64_t>(L, slab_bits / unit_bits);
+    const uint32_t G = (L + per_slab - 1u) / per_slab;
+    if (G > LDS_MAX_SLABS) return false;
+    const uint32_t units = (L + G - 1u) / G;                      // balanced slabs
+    lg.G = (L + units - 1u) / units;
+    lg.slab_rows = units * (dim == 2 ? 1u : L);
+    lg.slab_words = lg.slab_rows * lg.RW;
+    lg.dL = make_div(L);
+    lg.dslab = make_div(lg.slab_rows);
+    LdsPlan p{};
+    p.lg = lg;
+    const uint64_t N = lg.N;
+    p.wg = lg.G > 1u ? 256 : N <= 4096 ? 64 : N <= 16384 ? 128 : N < (1u << 18) ? 256 : 512;
+    uint32_t cap = 64u;
+    const uint64_t need = 2ull * (dim == 2 ? L : (uint64_t)L * L);  // bonds into a slab
+    while (cap < need) cap <<= 1;
+    p.imask = cap - 1u;
+    p.bnd_words = (dim == 2 ? 1u : L) * lg.RW;
+    p.ov_stride = lg.slab_rows * L;
+    p.lds_bytes = ((size_t)((lg.slab_words + 3u) & ~3u) + LDS_RING) * sizeof(uint32_t);
+    *out = p;
+    return true;
+}
+
+using LdsFn = void (*)(wolff::LdsArgs, uint32_t);
+
+static LdsFn lds_fn(int wg, int dim)
+{
+#define WOLFF_PICK_LDS(W) return dim == 2 ? wolff::lds_kernel<W, 2> : wolff::lds_kernel<W, 3>
+    switch (wg) {
+    case 64: WOLFF_PICK_LDS(64);
+    case 128: WOLFF_PICK_LDS(128);
+    case 512: WOLFF_PICK_LDS(512);
+    default: WOLFF_PICK_LDS(256);
+    }
+#undef WOLFF_PICK_LDS
+}
+
+static bool lds_fits(const wolff_sim* s)
+{
+    LdsPlan p;
+    return s->q == 0 && lds_plan(s->dim, (uint32_t)s->L, s->lds_slab_bits, &p) &&
+           (int)p.lg.G <= device_cus();
 }
 
 static int resolved_path(const wolff_sim* s)
@@ -365,6 +471,8 @@ static int team_size(const wolff_sim* s)
     return std::max(8, device_cus() / 4);
 }
 
+static void free_lds(wolff_sim* s);
+
 static void free_sim(wolff_sim* s)
 {
     if (!s) return;
@@ -375,14 +483,18 @@ static void free_sim(wolff_sim* s)
             (void)hipEventDestroy(e.b);
         }
     if (s->graph) (void)hipGraphExecDestroy(s->graph);
-    if (s->S) (void)hipFree(s->S);
-    if (s->ov) (void)hipFree(s->ov);
-    if (s->gq) (void)hipFree(s->gq);
+    if (!s->ext_buffers) {
+        if (s->S) (void)hipFree(s->S);
+        if (s->ov) (void)hipFree(s->ov);
+        if (s->d_rec) (void)hipFree(s->d_rec);
+    }
+    if (s->gq && !s->ext_queue) (void)hipFree(s->gq);
     if (s->d_rep) (void)hipFree(s->d_rep);
     if (s->d_order) (void)hipFree(s->d_order);
     if (s->d_next) (void)hipFree(s->d_next);
     if (s->d_ctl) (void)hipFree(s->d_ctl);
-    if (s->d_rec) (void)hipFree(s->d_rec);
+    free_lds(s);
+    if (s->abort_host) (void)hipHostFree(s->abort_host);
     if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
     delete s;
 }
@@ -434,6 +546,32 @@ static int pull_rep(wolff_sim* s, Rep* r)
     return WOLFF_OK;
 }
 
+// After the stream has drained: if a stop request is pending, clear it and,
+// when it stopped updates, take the update index and the record count from
+// the device (the updates that ran are exact; the rest never started).
+// Returns WOLFF_EABORTED once for a request that stopped updates.
+static int settle_abort(wolff_sim* s, const Rep& r)
+{
+    if (__atomic_load_n(s->abort_host, __ATOMIC_ACQUIRE) == 0u) return WOLFF_OK;
+    __atomic_store_n(s->abort_host, 0u, __ATOMIC_RELEASE);
+    if ((uint64_t)r.t == s->t) return WOLFF_OK;           // everything had run already
+    const uint64_t skipped = s->t - (uint64_t)r.t;
+    s->t = r.t;
+    s->rec_written = r.rec_count;
+    return fail(WOLFF_EABORTED, "stopped on request: " + std::to_string(skipped) +
+                                    " enqueued updates did not run");
+}
+
+// pull_rep, then settle a pending stop request.  *stopped receives the
+// result of settle_abort (WOLFF_OK or WOLFF_EABORTED).
+static int pull_rep_settled(wolff_sim* s, Rep* r, int* stopped)
+{
+    int rc = pull_rep(s, r);
+    if (rc) return rc;
+    *stopped = settle_abort(s, *r);
+    return WOLFF_OK;
+}
+
 static int measure_now(wolff_sim* s)
 {
     hipLaunchKernelGGL(wolff::measure_rep_kernel<1024>, dim3(1), dim3(1024), 0, s->stream, s->d_rep);
@@ -442,13 +580,26 @@ static int measure_now(wolff_sim* s)
     return WOLFF_OK;
 }
 
-static int create_sim(int dim, int L, int q, double J, double T, uint64_t seed, wolff_sim** out)
+static int create_sim(int dim, int L, int q, double J, double T, uint64_t seed,
+                      const wolff_buffers* ext, wolff_sim** out)
 {
     if (!out) return fail(WOLFF_EINVAL, "out is NULL");
     if (!valid_q(q)) return fail(WOLFF_EINVAL, "q must be 2..127 (or 0 for Ising)");
     uint64_t N = 0;
     int rc = check_params(dim, L, J, T, &N);
     if (rc) return rc;
+    if (ext) {
+        if (!ext->spins || !ext->overflow || !ext->records)
+            return fail(WOLFF_EINVAL, "wolff_buffers: spins, overflow and records are required");
+        if (ext->record_capacity < 1) return fail(WOLFF_EINVAL, "wolff_buffers: record_capacity < 1");
+        if ((ext->flags & ~(uint32_t)WOLFF_BUFFERS_KEEP_SPINS) != 0u)
+            return fail(WOLFF_EINVAL, "wolff_buffers: unknown flags");
+        if (ext->t0 > T_LIMIT) return fail(WOLFF_ERANGE, "wolff_buffers: t0 exceeds 2^32 - 2");
+        if ((uintptr_t)ext->spins % 16u || (uintptr_t)ext->overflow % 4u ||
+            (uintptr_t)ext->records % 8u || (uintptr_t)ext->team_queue % 8u)
+            return fail(WOLFF_EINVAL, "wolff_buffers: misaligned buffer (spins need 16-byte, "
+                                      "overflow 4-byte, records and team_queue 8-byte alignment)");
+    }
     wolff_sim* s = new (std::nothrow) wolff_sim();
     if (!s) return fail(WOLFF_ENOMEM, "host allocation failed");
     s->dim = dim;
@@ -467,7 +618,10 @@ static int create_sim(int dim, int L, int q, double J, double T, uint64_t seed, 
     // -35 % at L = 4096, -24 % at 3D L = 256)
     s->single_wg = N <= 4096 ? 64 : N <= 16384 ? 128 : N < (1ull << 20) ? 256 : 512;
     s->single_q = N < (1ull << 20) ? 2048 : 4096;
-    s->geo = make_geo(dim, (uint32_t)L);
+    // a caller's lattice is in site order; the library's own is tiled when
+    // L is a multiple of 16
+    s->geo = ext ? make_site_order_geo(dim, (uint32_t)L) : make_geo(dim, (uint32_t)L);
+    const uint64_t t0 = (ext && (ext->flags & WOLFF_BUFFERS_KEEP_SPINS)) ? ext->t0 : 0u;
 
 #define CREATE_TRY(expr)                                                                \
     do {                                                                                \
@@ -481,22 +635,41 @@ static int create_sim(int dim, int L, int q, double J, double T, uint64_t seed, 
 
     CREATE_TRY(hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking));
     s->stream = s->own_stream;
-    CREATE_TRY(hipMalloc(&s->S, padded_bytes(N)));
-    CREATE_TRY(hipMemsetAsync(s->S, 0, padded_bytes(N), s->stream));
-    CREATE_TRY(hipMalloc(&s->ov, N * sizeof(uint32_t)));
+    CREATE_TRY(hipHostMalloc((void**)&s->abort_host, sizeof(uint32_t),
+                             hipHostMallocMapped | hipHostMallocCoherent));
+    *s->abort_host = 0u;
+    CREATE_TRY(hipHostGetDevicePointer((void**)&s->abort_dev, s->abort_host, 0));
+    if (ext) {
+        s->ext_buffers = true;
+        s->S = ext->spins;
+        s->ov = ext->overflow;
+        s->d_rec = ext->records;
+        s->rec_cap = ext->record_capacity;
+        if (ext->team_queue) {
+            s->ext_queue = true;
+            s->gq = reinterpret_cast<unsigned long long*>(ext->team_queue);
+            CREATE_TRY(hipMemsetAsync(s->gq, 0, N * sizeof(unsigned long long), s->stream));
+        }
+    } else {
+        CREATE_TRY(hipMalloc(&s->S, padded_bytes(N)));
+        CREATE_TRY(hipMemsetAsync(s->S, 0, padded_bytes(N), s->stream));
+        CREATE_TRY(hipMalloc(&s->ov, N * sizeof(uint32_t)));
+        s->rec_cap = 1024;
+        CREATE_TRY(hipMalloc(&s->d_rec, s->rec_cap * sizeof(wolff_record)));
+    }
     CREATE_TRY(hipMalloc(&s->d_rep, sizeof(Rep)));
     CREATE_TRY(hipMalloc(&s->d_order, sizeof(uint32_t)));
     CREATE_TRY(hipMalloc(&s->d_next, sizeof(uint32_t)));
     CREATE_TRY(hipMalloc(&s->d_ctl, sizeof(TeamCtl)));
     CREATE_TRY(hipMemsetAsync(s->d_ctl, 0, sizeof(TeamCtl), s->stream));
     CREATE_TRY(hipMemsetAsync(s->d_order, 0, sizeof(uint32_t), s->stream));
-    s->rec_cap = 1024;
-    CREATE_TRY(hipMalloc(&s->d_rec, s->rec_cap * sizeof(wolff_record)));
 
-    hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((N + 255) / 256, 65536)),
-                       dim3(256), 0, s->stream, s->S, s->geo, dim, (uint32_t)seed,
-                       (uint32_t)(seed >> 32), (uint32_t)q);
-    CREATE_TRY(hipGetLastError());
+    if (!(ext && (ext->flags & WOLFF_BUFFERS_KEEP_SPINS))) {
+        hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((N + 255) / 256, 65536)),
+                           dim3(256), 0, s->stream, s->S, s->geo, dim, (uint32_t)seed,
+                           (uint32_t)(seed >> 32), (uint32_t)q);
+        CREATE_TRY(hipGetLastError());
+    }
 
     Rep r{};
     r.q = (uint32_t)q;
@@ -509,10 +682,13 @@ static int create_sim(int dim, int L, int q, double J, double T, uint64_t seed, 
     r.thr = s->thr;
     r.k0 = (uint32_t)seed;
     r.k1 = (uint32_t)(seed >> 32);
-    r.t = 0;
+    r.t = (uint32_t)t0;
+    r.t_norm = (uint32_t)t0;
     r.n_left = 0xFFFFFFFFu;
     r.measure = 1;
     r.err = 0;
+    r.abort = s->abort_dev;
+    s->t = t0;
     CREATE_TRY(copy_wait(s->stream, s->d_rep, &r, sizeof(Rep), hipMemcpyHostToDevice));
     if ((rc = measure_now(s)) != WOLFF_OK) {
         free_sim(s);
@@ -525,14 +701,21 @@ static int create_sim(int dim, int L, int q, double J, double T, uint64_t seed, 
 
 extern "C" int wolff_create(int dim, int L, double J, double T, uint64_t seed, wolff_sim** out)
 {
-    return create_sim(dim, L, 0, J, T, seed, out);
+    return create_sim(dim, L, 0, J, T, seed, nullptr, out);
 }
 
 extern "C" int wolff_create_potts(int dim, int L, int q, double J, double T, uint64_t seed,
                                   wolff_sim** out)
 {
     if (q == 0) return fail(WOLFF_EINVAL, "q must be 2..127");
-    return create_sim(dim, L, q, J, T, seed, out);
+    return create_sim(dim, L, q, J, T, seed, nullptr, out);
+}
+
+extern "C" int wolff_create_ex(int dim, int L, double J, double T, uint64_t seed,
+                               const wolff_buffers* ext, wolff_sim** out)
+{
+    if (!ext) return fail(WOLFF_EINVAL, "wolff_buffers is NULL");
+    return create_sim(dim, L, 0, J, T, seed, ext, out);
 }
 
 extern "C" int wolff_destroy(wolff_sim* s)
@@ -546,9 +729,19 @@ static int reserve_records(wolff_sim* s, uint64_t n)
 {
     const uint64_t need = s->rec_written + n;
     if (need <= s->rec_cap) return WOLFF_OK;
+    if (s->ext_buffers)
+        return fail(WOLFF_EINVAL, "the caller's record buffer holds " + std::to_string(s->rec_cap) +
+                                      " records and " + std::to_string(s->rec_written - s->rec_read) +
+                                      " are pending: drain them with wolff_observables");
     uint64_t cap = s->rec_cap;
     while (cap < need) cap *= 2;
-    HIP_TRY(hipStreamSynchronize(s->stream));
+    {   // the device's record count is the truth if a stop request cut work short
+        Rep cur;
+        int stopped = WOLFF_OK;
+        int rc0 = pull_rep_settled(s, &cur, &stopped);
+        if (rc0) return rc0;
+        if (stopped) return stopped;
+    }
     wolff_record* nrec = nullptr;
     HIP_TRY(hipMalloc(&nrec, cap * sizeof(wolff_record)));
     const uint64_t live = s->rec_written - s->rec_read;
@@ -574,6 +767,91 @@ static int ensure_team_queue(wolff_sim* s)
     HIP_TRY(hipStreamSynchronize(s->stream));
     HIP_TRY(hipMalloc(&s->gq, s->N * sizeof(unsigned long long)));
     HIP_TRY(hipMemsetAsync(s->gq, 0, s->N * sizeof(unsigned long long), s->stream));
+    return WOLFF_OK;
+}
+
+static void free_lds(wolff_sim* s)
+{
+    for (void* p : {(void*)s->lctl, (void*)s->linbox, (void*)s->ltail, (void*)s->lbnd, (void*)s->lov})
+        if (p) (void)hipFree(p);
+    s->lctl = nullptr;
+    s->linbox = nullptr;
+    s->ltail = nullptr;
+    s->lbnd = nullptr;
+    s->lov = nullptr;
+}
+
+// Team state of the LDS-resident path: allocated and zeroed on first use;
+// zeroed again whenever the update index is set (the inbox entries carry
+// the update index as their tag, so older entries must not survive a
+// rewind).
+static int lds_reset(wolff_sim* s)
+{
+    if (!s->lctl) return WOLFF_OK;
+    HIP_TRY(hipMemsetAsync(s->lctl, 0, sizeof(wolff::LdsCtl), s->stream));
+    HIP_TRY(hipMemsetAsync(s->linbox, 0, s->lbytes_inbox, s->stream));
+    HIP_TRY(hipMemsetAsync(s->ltail, 0, s->lbytes_tail, s->stream));
+    return WOLFF_OK;
+}
+
+static int ensure_lds(wolff_sim* s, const LdsPlan& p)
+{
+    if (s->lctl) return WOLFF_OK;
+    const uint32_t G = p.lg.G;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->lbytes_inbox = (size_t)G * (p.imask + 1u) * sizeof(unsigned long long);
+    s->lbytes_tail = (size_t)G * sizeof(uint32_t);
+    HIP_TRY(hipMalloc(&s->lctl, sizeof(wolff::LdsCtl)));
+    HIP_TRY(hipMalloc(&s->linbox, s->lbytes_inbox));
+    HIP_TRY(hipMalloc(&s->ltail, s->lbytes_tail));
+    HIP_TRY(hipMalloc(&s->lbnd, (size_t)G * p.bnd_words * sizeof(uint32_t)));
+    HIP_TRY(hipMalloc(&s->lov, (size_t)G * p.ov_stride * sizeof(uint32_t)));
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(lds_fn(p.wg, s->dim)),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes));
+    return lds_reset(s);
+}
+
+static int run_lds(wolff_sim* s, uint64_t n)
+{
+    LdsPlan p;
+    if (!lds_plan(s->dim, (uint32_t)s->L, s->lds_slab_bits, &p))
+        return fail(WOLFF_EINVAL, "lattice too large for the LDS path");
+    int rc = ensure_lds(s, p);
+    if (rc) return rc;
+    wolff::LdsArgs a{};
+    a.R = s->d_rep;
+    a.ctl = s->lctl;
+    a.inbox = s->linbox;
+    a.inbox_tail = s->ltail;
+    a.imask = p.imask;
+    a.bnd = s->lbnd;
+    a.bnd_words = p.bnd_words;
+    a.ov = s->lov;
+    a.ov_stride = p.ov_stride;
+    a.qmask = LDS_RING - 1u;
+    a.lg = p.lg;
+    // launches of about 2^27 sites of work (the expected clusters plus the
+    // slab load and write-back), at most 65536 updates
+    const double cl = s->csize_mean >= 0.0 ? s->csize_mean : (double)s->N;
+    const double work = cl + (double)s->N / 64.0 + 64.0;
+    const uint64_t chunk = (uint64_t)std::max(1.0, std::min(65536.0, (double)(1ull << 27) / work));
+    const LdsFn fn = lds_fn(p.wg, s->dim);
+    for (uint64_t done = 0; done < n;) {
+        const uint32_t m = (uint32_t)std::min<uint64_t>(chunk, n - done);
+        EventPair ev{};
+        if (s->profiling) {
+            if ((rc = get_event_pair(s, &ev))) return rc;
+            HIP_TRY(hipEventRecord(ev.a, s->stream));
+        }
+        hipLaunchKernelGGL(fn, dim3(p.lg.G), dim3(p.wg), p.lds_bytes, s->stream, a, m);
+        HIP_TRY(hipGetLastError());
+        if (s->profiling) {
+            HIP_TRY(hipEventRecord(ev.b, s->stream));
+            s->ev_grow.push_back(ev);
+        }
+        done += m;
+    }
+    s->tagged = false;                 // the slabs are written back as plain +-1 bytes
     return WOLFF_OK;
 }
 
@@ -664,6 +942,19 @@ extern "C" int wolff_set_tiles(wolff_sim* s, int wg, int queue_entries)
     return WOLFF_OK;
 }
 
+extern "C" int wolff_set_lds_slab(wolff_sim* s, uint32_t slab_bits)
+{
+    if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
+    if (slab_bits < 1024u || slab_bits > LDS_SLAB_BITS || (slab_bits & (slab_bits - 1u)) != 0u)
+        return fail(WOLFF_EINVAL, "slab_bits must be a power of two in [2^10, 2^20]");
+    if (slab_bits == s->lds_slab_bits) return WOLFF_OK;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    free_lds(s);                               // sizes follow the slab count
+    s->lds_slab_bits = slab_bits;
+    if (s->path == WOLFF_PATH_LDS && !lds_fits(s)) s->path = WOLFF_PATH_AUTO;
+    return WOLFF_OK;
+}
+
 extern "C" int wolff_set_graph(wolff_sim* s, int chunk)
 {
     if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
@@ -677,10 +968,19 @@ extern "C" int wolff_run(wolff_sim* s, uint64_t n)
     if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
     if (n == 0) return WOLFF_OK;
     if (s->t + n > T_LIMIT) return fail(WOLFF_ERANGE, "t + n_updates exceeds 2^32 - 2");
-    int rc = reserve_records(s, n);
-    if (rc) return rc;
+    int rc;
+    if (__atomic_load_n(s->abort_host, __ATOMIC_ACQUIRE) != 0u) {
+        // a stop request is pending: settle it before enqueueing anything
+        Rep cur;
+        int stopped = WOLFF_OK;
+        if ((rc = pull_rep_settled(s, &cur, &stopped))) return rc;
+        if (stopped) return stopped;
+    }
+    if ((rc = reserve_records(s, n))) return rc;
     const int path = resolved_path(s);
-    if (path == WOLFF_PATH_TEAM) {
+    if (path == WOLFF_PATH_LDS) {
+        if ((rc = run_lds(s, n))) return rc;
+    } else if (path == WOLFF_PATH_TEAM) {
         if ((rc = ensure_team_queue(s))) return rc;
         if (s->tagged) {
             // the team path reads plain bytes: drop the one-workgroup path's tags
@@ -724,6 +1024,14 @@ extern "C" int wolff_run(wolff_sim* s, uint64_t n)
             }
             done += m;
         }
+        if (s->ext_buffers && s->tagged) {
+            // the caller's lattice holds plain +-1 bytes between calls
+            const uint32_t nw = (uint32_t)((s->N + 3) / 4);
+            hipLaunchKernelGGL(wolff::plain_kernel, dim3(std::min<uint32_t>((nw + 255) / 256, 4096)),
+                               dim3(256), 0, s->stream, s->S, (uint32_t)s->N);
+            HIP_TRY(hipGetLastError());
+            s->tagged = false;
+        }
     }
     s->t += n;
     s->rec_written += n;
@@ -734,6 +1042,17 @@ extern "C" int wolff_synchronize(wolff_sim* s)
 {
     if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
     HIP_TRY(hipStreamSynchronize(s->stream));
+    if (__atomic_load_n(s->abort_host, __ATOMIC_ACQUIRE) == 0u) return WOLFF_OK;
+    Rep r;
+    int stopped = WOLFF_OK;
+    int rc = pull_rep_settled(s, &r, &stopped);
+    return rc ? rc : stopped;
+}
+
+extern "C" int wolff_abort(wolff_sim* s)
+{
+    if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
+    __atomic_store_n(s->abort_host, 1u, __ATOMIC_RELEASE);
     return WOLFF_OK;
 }
 
@@ -741,7 +1060,8 @@ extern "C" int wolff_observables(wolff_sim* s, wolff_record* out, uint64_t cap, 
 {
     if (!s || (!out && cap > 0)) return fail(WOLFF_EINVAL, "NULL argument");
     Rep r;
-    int rc = pull_rep(s, &r);
+    int stopped = WOLFF_OK;
+    int rc = pull_rep_settled(s, &r, &stopped);
     if (rc) return rc;
     const uint64_t live = s->rec_written - s->rec_read;
     const uint64_t k = std::min(cap, live);
@@ -772,6 +1092,8 @@ extern "C" int wolff_observables(wolff_sim* s, wolff_record* out, uint64_t cap, 
     }
     if (push && (rc = push_rep(s, r))) return rc;
     if (bad) return fail(WOLFF_ESTATE, err_message(bad_bits));
+    if (stopped) return fail(WOLFF_EABORTED, "stopped on request; the records of the updates "
+                                             "that ran were returned");
     return WOLFF_OK;
 }
 
@@ -779,7 +1101,8 @@ extern "C" int wolff_get_info(wolff_sim* s, wolff_info* out)
 {
     if (!s || !out) return fail(WOLFF_EINVAL, "NULL argument");
     Rep r;
-    int rc = pull_rep(s, &r);
+    int stopped = WOLFF_OK;
+    int rc = pull_rep_settled(s, &r, &stopped);
     if (rc) return rc;
     out->dim = s->dim;
     out->L = s->L;
@@ -795,14 +1118,19 @@ extern "C" int wolff_get_info(wolff_sim* s, wolff_info* out)
     out->mag = r.M;
     out->bond_sum = r.B;
     out->records_pending = s->rec_written - s->rec_read;
-    return WOLFF_OK;
+    return stopped;
 }
 
 extern "C" int wolff_get_spins(wolff_sim* s, int8_t* host, uint64_t n)
 {
     if (!s || !host) return fail(WOLFF_EINVAL, "NULL argument");
     if (n != s->N) return fail(WOLFF_EINVAL, "n must equal the number of sites");
-    return copy_spins_out(s->stream, s->geo, s->dim, s->S, host, n, s->q);
+    int rc = copy_spins_out(s->stream, s->geo, s->dim, s->S, host, n, s->q);
+    if (rc || __atomic_load_n(s->abort_host, __ATOMIC_ACQUIRE) == 0u) return rc;
+    Rep r;
+    int stopped = WOLFF_OK;
+    rc = pull_rep_settled(s, &r, &stopped);
+    return rc ? rc : stopped;
 }
 
 extern "C" int wolff_set_spins(wolff_sim* s, const int8_t* host, uint64_t n, uint64_t t)
@@ -818,7 +1146,8 @@ extern "C" int wolff_set_spins(wolff_sim* s, const int8_t* host, uint64_t n, uin
             if (host[i] != 1 && host[i] != -1) return fail(WOLFF_EINVAL, "spins must be +1 or -1");
     }
     Rep r;
-    int rc = pull_rep(s, &r);
+    int stopped = WOLFF_OK;
+    int rc = pull_rep_settled(s, &r, &stopped);
     if (rc) return rc;
     if ((rc = copy_spins_in(s->stream, s->geo, s->dim, host, s->S, n))) return rc;
     r.t = (uint32_t)t;
@@ -830,18 +1159,22 @@ extern "C" int wolff_set_spins(wolff_sim* s, const int8_t* host, uint64_t n, uin
     s->t = t;
     s->rec_read = s->rec_written = 0;
     if ((rc = push_rep(s, r))) return rc;
-    return measure_now(s);
+    if ((rc = lds_reset(s))) return rc;
+    if ((rc = measure_now(s))) return rc;
+    return stopped;
 }
 
 extern "C" int wolff_set_measure(wolff_sim* s, int on)
 {
     if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
     Rep r;
-    int rc = pull_rep(s, &r);
+    int stopped = WOLFF_OK;
+    int rc = pull_rep_settled(s, &r, &stopped);
     if (rc) return rc;
     s->measure = on ? 1 : 0;
     r.measure = (uint32_t)s->measure;
-    return push_rep(s, r);
+    if ((rc = push_rep(s, r))) return rc;
+    return stopped;
 }
 
 extern "C" int wolff_set_stream(wolff_sim* s, void* hip_stream)
@@ -855,8 +1188,12 @@ extern "C" int wolff_set_stream(wolff_sim* s, void* hip_stream)
 extern "C" int wolff_set_path(wolff_sim* s, int path, int workgroups)
 {
     if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
-    if (path != WOLFF_PATH_AUTO && path != WOLFF_PATH_SINGLE && path != WOLFF_PATH_TEAM)
+    if (path != WOLFF_PATH_AUTO && path != WOLFF_PATH_SINGLE && path != WOLFF_PATH_TEAM &&
+        path != WOLFF_PATH_LDS)
         return fail(WOLFF_EINVAL, "unknown path");
+    if (path == WOLFF_PATH_LDS && !lds_fits(s))
+        return fail(WOLFF_EINVAL, "the LDS path takes Ising lattices whose slabs fit the device "
+                                  "(rows or planes of at most 2^20 bits, at most 64 slabs)");
     if (workgroups < 0 || workgroups > 65536) return fail(WOLFF_EINVAL, "bad workgroup count");
     s->path = path;
     s->team_wgs = workgroups;

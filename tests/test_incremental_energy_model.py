@@ -43,15 +43,28 @@ def parity(dim, L, i):
     return int(sum(np.unravel_index(i, (L,) * dim, order="F"))) & 1
 
 
-def grow_and_count(dim, L, S, active, seed_site, rng, max_batch):
+def wraps(dim, L, i, m):
+    """Slot m of site i (+x, -x, +y, -y, +z, -z) crosses the periodic boundary."""
+    c = np.unravel_index(i, (L,) * dim, order="F")
+    mu, up = m // 2, m % 2 == 0
+    return c[mu] == (L - 1 if up else 0)
+
+
+def grow_and_count(dim, L, S, active, seed_site, rng, max_batch, face_rule=False):
     """Grow the cluster of seed_site with the step structure; returns
-    (members, n_anti, n_inner).  active[(b, mu)] is the bond (b, b + e_mu)."""
+    (members, n_anti, n_inner).  active[(b, mu)] is the bond (b, b + e_mu).
+
+    face_rule (the odd-L form): a wrap-around bond never counts towards
+    n_inner; instead every expanded member on a last face (a coordinate equal
+    to L - 1) is listed, and once the cluster is complete each listed member
+    counts its +mu wrap-around neighbours that are members."""
     N = L ** dim
     s0 = int(S[seed_site])
     member = np.zeros(N, bool)
     expanded = np.zeros(N, bool)
     member[seed_site] = True
     pending = [seed_site]                  # claimed, not yet expanded
+    faces = []                             # expanded members on a last face (face_rule)
     n_anti = n_inner = 0
     while pending:
         k = int(rng.integers(1, max_batch + 1))
@@ -70,7 +83,7 @@ def grow_and_count(dim, L, S, active, seed_site, rng, max_batch):
                 seen_member = visible[kk] or (member[kk] and rng.random() < 0.5)
                 if not seen_member and int(S[kk]) != s0:
                     n_anti += 1
-                if member[kk] and expanded[kk]:
+                if member[kk] and expanded[kk] and not (face_rule and wraps(dim, L, j, m)):
                     n_inner += 1
                 if int(S[kk]) == s0 and not member[kk]:
                     b = j if m % 2 == 0 else kk
@@ -80,17 +93,24 @@ def grow_and_count(dim, L, S, active, seed_site, rng, max_batch):
         for j in batch:                    # odd sites: after every read of the step
             if parity(dim, L, j) == 1:
                 expanded[j] = True
+            if face_rule and any(c == L - 1 for c in np.unravel_index(j, (L,) * dim, order="F")):
+                faces.append(j)
         pending.extend(claimed_now)
+    for j in faces:                        # the cluster is complete: wrap-around bonds
+        nb = neighbours(dim, L, j)
+        for m in range(0, 2 * dim, 2):
+            if wraps(dim, L, j, m) and member[nb[m]]:
+                n_inner += 1
     return member, n_anti, n_inner
 
 
-def one_case(dim, L, p, rng, max_batch):
+def one_case(dim, L, p, rng, max_batch, face_rule=False):
     N = L ** dim
     S = rng.choice(np.array([-1, 1], dtype=np.int8), size=N)
     active = {(b, mu): rng.random() < p for b in range(N) for mu in range(dim)}
     seed = int(rng.integers(N))
     s0 = int(S[seed])
-    member, n_anti, n_inner = grow_and_count(dim, L, S, active, seed, rng, max_batch)
+    member, n_anti, n_inner = grow_and_count(dim, L, S, active, seed, rng, max_batch, face_rule)
     C = int(member.sum())
     B0 = bond_sum(dim, L, S)
     S1 = S.copy()
@@ -116,3 +136,14 @@ def test_odd_L_breaks_the_parity_rule():
         exact, counted = one_case(2, 5, 0.9, rng, max_batch=4)
         bad += exact != counted
     assert bad > 0
+
+
+@pytest.mark.parametrize("dim,L", [(2, 3), (2, 5), (2, 7), (3, 3), (3, 5), (2, 4), (3, 2), (2, 6)])
+def test_face_rule_counts_every_L(dim, L):
+    # with wrap-around bonds counted from the last faces once the cluster is
+    # complete, the count is exact for odd L, and stays exact for even L
+    rng = np.random.default_rng(2000 * dim + L)
+    for trial in range(60):
+        p = (0.3, 0.6, 0.9, 1.0)[trial % 4]
+        exact, counted = one_case(dim, L, p, rng, max_batch=1 + trial % 7, face_rule=True)
+        assert exact == counted, (dim, L, trial)
