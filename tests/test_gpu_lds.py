@@ -81,13 +81,16 @@ def test_slabs(dim, L, T, n, slab, measure):
     check(dim, L, T, 300 + L, n, slab, measure)
 
 
-@pytest.mark.parametrize("slab", [None, 1024])
-def test_cold_lattices_cross_slabs_and_overflow(slab):
+@pytest.mark.parametrize("split", [False, True])
+def test_cold_lattices_cross_slabs_and_overflow(split):
     # ordered start below T_c: clusters of most of the lattice, frontiers far
-    # beyond the LDS ring, and (with small slabs) many crossings per update
-    for dim, L, T, n in [(2, 256, 1.5, 20), (3, 40, 3.0, 12), (2, 512, 1.8, 6)]:
+    # beyond the LDS ring, and (split) many crossings per update: the
+    # smallest slab that keeps at most 64 slabs of whole rows / planes
+    # (64, 40 and 32 slabs here)
+    for dim, L, T, n, small in [(2, 256, 1.5, 20, 1024), (3, 40, 3.0, 12, 4096),
+                                (2, 512, 1.8, 6, 8192)]:
         N = L ** dim
-        ref = check(dim, L, T, 77, n, slab, True, np.ones(N, dtype=np.int8))
+        ref = check(dim, L, T, 77, n, small if split else None, True, np.ones(N, dtype=np.int8))
         assert ref[:, 2].max() > N // 2
 
 
