@@ -132,6 +132,38 @@ typedef struct {
 int wolff_create_ex(int dim, int L, double J, double T, uint64_t seed,
                     const wolff_buffers *buffers, wolff_sim **out);
 
+/* ------------------------------------------------ no-allocation variant */
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * updates as wolff_create_ex + wolff_set_path(WOLFF_PATH_SINGLE) +
+ * wolff_set_measure(measure) + wolff_run(n_updates) + wolff_synchronize on
+ * the same buffers, records and spins identical, but the call allocates
+ * nothing: the lattice descriptor and the frontier overflow stack live in a
+ * fixed device array of the library (about 4 MiB + 1 KiB, held by every
+ * device the library runs on until the process ends).
+ *   spins     device pointer, 16-byte aligned, >= L^dim bytes: the lattice in
+ *             site order as int8 +1 / -1.  With WOLFF_BUFFERS_KEEP_SPINS in
+ *             flags it holds the state at update index t0 on entry;
+ *             otherwise it is filled iid from `seed` and t0 is ignored (the
+ *             run starts at update 0).  On return it holds the state after
+ *             the last update, as plain +1 / -1 bytes.
+ *   records   device pointer, 8-byte aligned, >= n_updates records: the
+ *             record of update k of this call is records[k] (may be NULL
+ *             when n_updates is 0).
+ *   measure   0: "update only" records (bond_sum = WOLFF_NOT_MEASURED).
+ *   hip_stream  the stream the work is ordered on (NULL: the null stream);
+ *             the call waits for it before returning.
+ * L^dim must be <= WOLFF_NOALLOC_MAX_SITES (WOLFF_EINVAL otherwise, before
+ * anything runs).  Every call on one device uses the same fixed array:
+ * calls that overlap on a device (other threads, other streams) race and
+ * must be serialised by the caller.  Ising only (no Potts).  Errors as
+ * wolff_create_ex and wolff_run; WOLFF_ESTATE if a device-side check
+ * failed. */
+#define WOLFF_NOALLOC_MAX_SITES (1u << 20)
+int wolff_run_noalloc(int dim, int L, double J, double T, uint64_t seed,
+                      int8_t *spins, uint64_t t0, uint32_t flags, int measure,
+                      uint64_t n_updates, wolff_record *records, void *hip_stream);
+
 /* The q-state Potts model, H = -J sum_<ij> delta(s_i, s_j), colours
  * 0 .. q-1 (the extension Section 6 calls straightforward), 2 <= q <= 127:
  * bonds between equal colours are active with p = 1 - exp(-J/T) (the Ising

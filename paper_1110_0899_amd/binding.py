@@ -85,6 +85,7 @@ SIGNATURES = {
     "wolff_create": (_I, [_I, _I, _D, _D, _U64, ctypes.POINTER(_P)]),
     "wolff_create_potts": (_I, [_I, _I, _I, _D, _D, _U64, ctypes.POINTER(_P)]),
     "wolff_create_ex": (_I, [_I, _I, _D, _D, _U64, ctypes.POINTER(Buffers), ctypes.POINTER(_P)]),
+    "wolff_run_noalloc": (_I, [_I, _I, _D, _D, _U64, _P, _U64, ctypes.c_uint32, _I, _U64, _P, _P]),
     "wolff_destroy": (_I, [_P]),
     "wolff_abort": (_I, [_P]),
     "wolff_run": (_I, [_P, _U64]),
@@ -272,6 +273,17 @@ class Simulation:
                                          ctypes.byref(m), ctypes.byref(mn)), "wolff_profile_read")
         return {"grow_ms": g.value, "grow_launches": gn.value,
                 "measure_ms": m.value, "measure_launches": mn.value}
+
+
+def run_noalloc(dim: int, L: int, J: float, T: float, seed: int, spins_ptr: int, n_updates: int,
+                records_ptr: int, t0: int | None = None, measure: bool = True, stream=None):
+    """wolff_run_noalloc on caller-owned device memory (raw addresses, e.g.
+    tensor.data_ptr()); t0 given: the spins buffer holds the state at t0."""
+    flags = BUFFERS_KEEP_SPINS if t0 is not None else 0
+    _check(load().wolff_run_noalloc(dim, L, float(J), float(T), int(seed), int(spins_ptr),
+                                    int(t0 or 0), flags, 1 if measure else 0, int(n_updates),
+                                    int(records_ptr) if records_ptr else None,
+                                    _stream_handle(stream)), "wolff_run_noalloc")
 
 
 class Batch:

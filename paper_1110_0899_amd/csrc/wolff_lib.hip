@@ -9,6 +9,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1812,5 +1813,143 @@ extern "C" int wolff_server_get_stats(wolff_server* v, wolff_server_stats* out)
     out->updates = v->updates;
     out->added_spins = v->added;
     out->gpu_ms = v->gpu_ms;
+    return WOLFF_OK;
+}
+
+// ============================================== no-allocation entry point
+// wolff_run_noalloc keeps everything the kernels need beyond the caller's
+// spins and records in `scratch`, a fixed array in device memory: the
+// lattice descriptor, the replica list and work counter of the
+// one-workgroup kernel, and its frontier overflow stack (4 bytes per site).
+// Every device the library runs on holds its own copy for the life of the
+// process, and every call on that device shares it, so calls that overlap
+// on one device (different streams, different threads) race.
+static constexpr size_t NOALLOC_HEADER = 1024;     // descriptor, list, counter
+static constexpr size_t NOALLOC_BYTES =
+    NOALLOC_HEADER + (size_t)WOLFF_NOALLOC_MAX_SITES * sizeof(uint32_t);
+static_assert(sizeof(Rep) + 512 <= NOALLOC_HEADER, "descriptor does not fit the header");
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+// Device address of `scratch` on each device, taken once per device with
+// that device current (the array's name is not a device address in host
+// code).
+static constexpr int NOALLOC_MAX_DEVICES = 64;
+static unsigned char* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+static std::mutex g_scratch_mu;
+
+static int scratch_address(unsigned char** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(WOLFF_EDEVICE, "device index beyond the no-allocation table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(WOLFF_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_dev[dev] = static_cast<unsigned char*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return WOLFF_OK;
+}
+
+namespace wolff {
+// The descriptor, the one-entry replica list and the work counter, written
+// on the stream (no host copy into device memory).
+__global__ void noalloc_setup_kernel(Rep* R, Rep init, uint32_t* order, uint32_t* next)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *R = init;
+        order[0] = 0u;
+        next[0] = 0u;
+    }
+}
+
+// The error bits and update index of the descriptor, for the host.
+__global__ void noalloc_status_kernel(const Rep* R, uint32_t* out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        out[0] = R->err;
+        out[1] = R->t;
+    }
+}
+}  // namespace wolff
+
+extern "C" int wolff_run_noalloc(int dim, int L, double J, double T, uint64_t seed,
+                                 int8_t* spins, uint64_t t0, uint32_t flags, int measure,
+                                 uint64_t n_updates, wolff_record* records, void* hip_stream)
+{
+    uint64_t N = 0;
+    int rc = check_params(dim, L, J, T, &N);
+    if (rc) return rc;
+    if (N > WOLFF_NOALLOC_MAX_SITES)
+        return fail(WOLFF_EINVAL, "wolff_run_noalloc: L^dim = " + std::to_string(N) +
+                                      " exceeds the fixed scratch limit of " +
+                                      std::to_string(WOLFF_NOALLOC_MAX_SITES) + " sites");
+    if (!spins || (uintptr_t)spins % 16u)
+        return fail(WOLFF_EINVAL, "wolff_run_noalloc: spins must be a 16-byte aligned device pointer");
+    if (n_updates > 0 && (!records || (uintptr_t)records % 8u))
+        return fail(WOLFF_EINVAL, "wolff_run_noalloc: records must be an 8-byte aligned device pointer");
+    if ((flags & ~(uint32_t)WOLFF_BUFFERS_KEEP_SPINS) != 0u)
+        return fail(WOLFF_EINVAL, "wolff_run_noalloc: unknown flags");
+    const bool keep = (flags & WOLFF_BUFFERS_KEEP_SPINS) != 0u;
+    const uint64_t t_start = keep ? t0 : 0u;
+    if (t_start > T_LIMIT || n_updates > T_LIMIT - t_start)
+        return fail(WOLFF_ERANGE, "wolff_run_noalloc: t0 + n_updates exceeds 2^32 - 2");
+    unsigned char* base = nullptr;
+    if ((rc = scratch_address(&base))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    Rep* R = reinterpret_cast<Rep*>(base);
+    uint32_t* order = reinterpret_cast<uint32_t*>(base + 512);
+    uint32_t* next = order + 1;
+    uint32_t* status = order + 2;
+    uint32_t* ov = reinterpret_cast<uint32_t*>(base + NOALLOC_HEADER);
+
+    const Geo g = make_site_order_geo(dim, (uint32_t)L);
+    if (!keep) {
+        hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((N + 255) / 256, 65536)),
+                           dim3(256), 0, st, spins, g, dim, (uint32_t)seed, (uint32_t)(seed >> 32), 0u);
+        HIP_TRY(hipGetLastError());
+    }
+    Rep r{};
+    r.S = spins;
+    r.ov = ov;
+    r.rec = records;
+    r.rec_count = 0;
+    r.geo = g;
+    r.dim = dim;
+    r.thr = bond_threshold(J, T);
+    r.k0 = (uint32_t)seed;
+    r.k1 = (uint32_t)(seed >> 32);
+    r.t = (uint32_t)t_start;
+    r.t_norm = (uint32_t)t_start;
+    r.n_left = (uint32_t)n_updates;
+    r.measure = measure ? 1u : 0u;
+    r.abort = nullptr;
+    hipLaunchKernelGGL(wolff::noalloc_setup_kernel, dim3(1), dim3(64), 0, st, R, r, order, next);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(wolff::measure_rep_kernel<1024>, dim3(1), dim3(1024), 0, st, R);
+    HIP_TRY(hipGetLastError());
+    if (n_updates > 0) {
+        // the one-workgroup path with the tiles wolff_create picks for this size
+        const int wg = N <= 4096 ? 64 : N <= 16384 ? 128 : N < (1ull << 20) ? 256 : 512;
+        const uint32_t qe = N < (1ull << 20) ? 2048u : 4096u;
+        HIP_TRY(launch_batch(wg, dim, 1u, qe, st, R, order, 1u, next, 0u));
+        // plain +-1 bytes in the caller's lattice (the incremental bond sum tags members)
+        hipLaunchKernelGGL(wolff::plain_kernel, dim3(std::min<uint64_t>((N / 4 + 255) / 256 + 1, 4096)),
+                           dim3(256), 0, st, spins, (uint32_t)N);
+        HIP_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(wolff::noalloc_status_kernel, dim3(1), dim3(64), 0, st, R, status);
+    HIP_TRY(hipGetLastError());
+    uint32_t host_status[2] = {0u, 0u};
+    HIP_TRY(hipMemcpyAsync(host_status, status, sizeof(host_status), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (host_status[0] != 0u) return fail(WOLFF_ESTATE, err_message(host_status[0]));
+    if ((uint64_t)host_status[1] != t_start + n_updates)
+        return fail(WOLFF_ESTATE, "wolff_run_noalloc: the kernel stopped at update " +
+                                      std::to_string(host_status[1]));
     return WOLFF_OK;
 }

@@ -71,3 +71,10 @@ def test_create_potts_rejects_bad_q(lib, q):
     h = ctypes.c_void_p()
     assert lib.wolff_create_potts(2, 8, q, 1.0, 1.0, 1, ctypes.byref(h)) == binding.EINVAL
     assert not h.value
+
+
+def test_noalloc_rejects_sizes_beyond_its_fixed_array(lib):
+    # the size is checked before any device call
+    for dim, L in ((2, 1025), (3, 102)):
+        assert lib.wolff_run_noalloc(dim, L, 1.0, 2.0, 1, None, 0, 0, 1, 1, None, None) == binding.EINVAL
+        assert b"scratch" in lib.wolff_last_error()
