@@ -114,6 +114,7 @@ __device__ __forceinline__ void flag_wait_failure(LdsCtl* ctl)
 template <typename F>
 __device__ __forceinline__ void grid_barrier(LdsCtl* ctl, uint32_t G, F last)
 {
+    __syncthreads();            // the workgroup's writes happen before thread 0 arrives
     if (threadIdx.x == 0) {
         if (G == 1) {
             last();
@@ -215,10 +216,164 @@ __device__ __forceinline__ void slab_counts(const uint32_t* bits, const LdsGeo& 
     nneg = neg;
 }
 
-template <int WG, int DIM>
+// Neighbour slot m of site j (+x, -x, +y, -y[, +z, -z]) as (row, column).
+template <int DIM>
+__device__ __forceinline__ void lds_neighbour(const LdsGeo& lg, uint32_t j, uint32_t m, uint32_t& nr,
+                                              uint32_t& nc)
+{
+    const uint32_t L = lg.L;
+    const uint32_t r = lg.dL.div(j);
+    const uint32_t x = j - r * L;
+    const uint32_t mu = m >> 1;
+    const bool plus = (m & 1u) == 0u;
+    if (mu == 0u) {
+        nr = r;
+        nc = plus ? ((x + 1u == L) ? 0u : x + 1u) : ((x == 0u) ? L - 1u : x - 1u);
+        return;
+    }
+    nc = x;
+    if (DIM == 2) {
+        nr = plus ? ((r + 1u == L) ? 0u : r + 1u) : ((r == 0u) ? L - 1u : r - 1u);
+    } else {
+        const uint32_t z = lg.dL.div(r);
+        const uint32_t y = r - z * L;
+        if (mu == 1u)
+            nr = plus ? ((y + 1u == L) ? r + 1u - L : r + 1u) : ((y == 0u) ? r + L - 1u : r - 1u);
+        else
+            nr = plus ? ((z + 1u == L) ? y : r + L) : ((z == 0u) ? r + lg.rows - L : r - L);
+    }
+}
+
+// Claims of up to NS local bits for a cluster of seed bit b0; every atomic
+// is issued before any result is used.
+template <int NS>
+__device__ __forceinline__ void claim_bits(uint32_t* bits, const uint32_t ba[NS], const bool act[NS],
+                                           uint32_t b0, bool won[NS])
+{
+    uint32_t old[NS];
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+        const uint32_t msk = 1u << (ba[m] & 31u);
+        old[m] = 0u;
+        if (act[m])
+            old[m] = (b0 == 0u) ? atomicOr(&bits[ba[m] >> 5], msk) : atomicAnd(&bits[ba[m] >> 5], ~msk);
+    }
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+        const uint32_t msk = 1u << (ba[m] & 31u);
+        won[m] = act[m] && (((old[m] & msk) != 0u) == (b0 != 0u));
+    }
+}
+
+// Second half of a growth step, for NS neighbour slots per lane: compaction
+// of the claimed sites and of the messages (to the previous / next slab),
+// the step's net change of P (before any of its messages is written), the
+// messages, and the claimed sites appended to the ring or the overflow stack.
+template <int WG, int NS>
+__device__ __forceinline__ void lds_publish(const LdsArgs& a, LdsCtl* ctl, uint32_t* q, uint32_t* wave_cnt,
+                                            uint32_t* wave_snd, uint32_t* sh, gword* ov, const bool won[NS],
+                                            const bool snd[NS], const bool to_next[NS],
+                                            const uint32_t nb[NS], uint32_t nproc,
+                                            unsigned long long epoch, uint32_t b0, uint32_t gprev,
+                                            uint32_t gnext, uint32_t G, uint32_t QC, uint32_t& head,
+                                            uint32_t& tail, uint32_t& ovn, uint32_t& claims)
+{
+    constexpr int NW = WG / WAVE;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (WAVE - 1);
+    const uint32_t wv = tid / WAVE;
+    uint32_t pos[NS], spos[NS];
+    uint32_t wtot = 0u;
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+        const uint64_t mask = __ballot(won[m]);
+        pos[m] = wtot + lane_prefix(mask);
+        wtot += (uint32_t)__popcll(mask);
+    }
+    uint32_t sprev = 0u, snext = 0u;
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+        const uint64_t mp = __ballot(snd[m] && !to_next[m]);
+        const uint64_t mn = __ballot(snd[m] && to_next[m]);
+        spos[m] = to_next[m] ? snext + lane_prefix(mn) : sprev + lane_prefix(mp);
+        sprev += (uint32_t)__popcll(mp);
+        snext += (uint32_t)__popcll(mn);
+    }
+    if (lane == 0) {
+        wave_cnt[wv] = wtot;
+        wave_snd[wv] = sprev;
+        wave_snd[NW + wv] = snext;
+    }
+    __syncthreads();
+    uint32_t before = 0u, total = 0u, pb = 0u, ptot = 0u, nbf = 0u, ntot = 0u;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const uint32_t c = wave_cnt[w], cp = wave_snd[w], cn = wave_snd[NW + w];
+        const bool lower = (uint32_t)w < wv;
+        before += lower ? c : 0u;
+        pb += lower ? cp : 0u;
+        nbf += lower ? cn : 0u;
+        total += c;
+        ptot += cp;
+        ntot += cn;
+    }
+    if (G > 1u) {
+        if (tid == 0) {
+            const long long delta = (long long)total + (long long)(ptot + ntot) - (long long)nproc;
+            if (ptot + ntot > 0u) {
+                // the units of the messages must be in P before a
+                // receiver can consume them: wait for the addition
+                sh[7] = (uint32_t)__hip_atomic_fetch_add(&ctl->P, (unsigned long long)delta,
+                                                         __ATOMIC_RELAXED, SCOPE_AGENT);
+                sh[5] = ptot ? __hip_atomic_fetch_add(&a.inbox_tail[gprev], ptot, __ATOMIC_RELAXED, SCOPE_AGENT) : 0u;
+                sh[6] = ntot ? __hip_atomic_fetch_add(&a.inbox_tail[gnext], ntot, __ATOMIC_RELAXED, SCOPE_AGENT) : 0u;
+            } else if (delta != 0) {
+                __hip_atomic_fetch_add(&ctl->P, (unsigned long long)delta, __ATOMIC_RELAXED, SCOPE_AGENT);
+            }
+        }
+        if (ptot + ntot > 0u) {
+            __syncthreads();
+            const uint32_t basep = sh[5], basen = sh[6];
+            const unsigned long long word = epoch | (b0 ? MSG_S0_NEG : 0u);
+#pragma unroll
+            for (int m = 0; m < NS; ++m) {
+                if (snd[m]) {
+                    const uint32_t dst = to_next[m] ? gnext : gprev;
+                    const uint32_t slot = to_next[m] ? basen + nbf + spos[m] : basep + pb + spos[m];
+                    __hip_atomic_store(&a.inbox[(size_t)dst * (a.imask + 1u) + (slot & a.imask)],
+                                       word | nb[m], __ATOMIC_RELAXED, SCOPE_AGENT);
+                }
+            }
+        }
+    }
+    // append the claimed sites to the ring (or the overflow stack); the
+    // counters move by selects, not through a reference chosen by branch
+    // (which the compiler would keep in scratch memory)
+    const bool fits = total <= QC - (tail - head);
+    const uint32_t qbase = tail + before, obase = ovn + before;
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+        if (won[m]) {
+            if (fits)
+                q[(qbase + pos[m]) & a.qmask] = nb[m];
+            else
+                ov[obase + pos[m]] = nb[m];
+        }
+    }
+    tail += fits ? total : 0u;
+    ovn += fits ? 0u : total;
+    claims += total;
+}
+
+// MULTI: the lattice spans several slabs (G > 1, messages and grid
+// barriers); otherwise one workgroup holds it all and every team-only branch
+// compiles away.
+template <int WG, int DIM, bool MULTI>
 __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates)
 {
     constexpr int NW = WG / WAVE;
+    constexpr int D2 = 2 * DIM;
+    constexpr uint32_t BOND_SITES = (uint32_t)(WG / D2);    // sites of a one-lane-per-bond step
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t wave_cnt[NW];
     __shared__ uint32_t wave_snd[2 * NW];
@@ -233,7 +388,7 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
     const uint32_t lane = tid & (WAVE - 1);
     const uint32_t wv = tid / WAVE;
     const uint32_t g = blockIdx.x;
-    const uint32_t G = lg.G;
+    const uint32_t G = MULTI ? lg.G : 1u;
     const uint32_t r0 = g * lg.slab_rows;
     const uint32_t nrows = min(lg.slab_rows, lg.rows - r0);
     const uint32_t L = lg.L;
@@ -287,9 +442,17 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
     const uint64_t rec0 = R->rec_count;
     __syncthreads();
 
+    // one workgroup (G = 1): M, B and the error bits in thread 0's registers
+    int64_t M1 = R->M, B1 = R->B;
+    uint32_t err1 = 0u;
+    const uint32_t* abort_flag = R->abort;
     uint32_t done = 0u;
     for (; done < n; ++done) {
         const uint32_t t = t0 + done;
+        // G = 1: the stop request is read now and used after the update, so
+        // that the read's latency hides behind the growth
+        uint32_t abort_now = 0u;
+        if (G == 1u && tid == 0) abort_now = abort_requested(abort_flag);
         const unsigned long long epoch = (unsigned long long)(t + 1u) << 32;
         const uint32_t s = seed_site(k0, k1, t, lg.N);                // step (i)
         const uint32_t srow = lg.dL.div(s);
@@ -424,146 +587,90 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
             }
             if (avail == 0u) continue;                            // (G > 1) poll again
 
-            // ---- one growth step over up to WG frontier sites (steps (ii)-(iii))
+            // ---- one growth step (steps (ii)-(iii)).  A wide frontier takes
+            // one lane per site (every neighbour of the site in that lane,
+            // up to WG sites); a narrow one takes one lane per bond (up to
+            // WG / 2d sites), so that its Philox blocks, neighbour reads and
+            // claims are spread over 2d times more lanes and the step's
+            // chain is one block long instead of 1 + d.
             const uint32_t b0 = sh[1];
-            const uint32_t nproc = min(avail, (uint32_t)WG);
-            const bool active = tid < nproc;
-            const uint32_t j = active ? q[(head + tid) & a.qmask] : 0u;
-            head += nproc;
             const bool look = G > 1u && (nstep++ & 3u) == 0u;
             uint32_t it_async = 0u;
             if (look && tid == 0) it_async = ld_agent(&a.inbox_tail[g]);   // used at the end of the step
-            // coordinates and neighbours (logical indices nb, rows nr, columns nx)
-            const uint32_t r = lg.dL.div(j);
-            const uint32_t x = j - r * L;
-            uint32_t nb[2 * DIM], nr[2 * DIM], ncol[2 * DIM];
-            const uint32_t xp = (x + 1u == L) ? 0u : x + 1u;
-            const uint32_t xm = (x == 0u) ? L - 1u : x - 1u;
-            nr[0] = r; ncol[0] = xp;
-            nr[1] = r; ncol[1] = xm;
-            if (DIM == 2) {
-                nr[2] = (r + 1u == L) ? 0u : r + 1u;
-                nr[3] = (r == 0u) ? L - 1u : r - 1u;
-                ncol[2] = ncol[3] = x;
-            } else {
-                const uint32_t z = lg.dL.div(r);
-                const uint32_t y = r - z * L;
-                nr[2] = (y + 1u == L) ? r + 1u - L : r + 1u;
-                nr[3] = (y == 0u) ? r + L - 1u : r - 1u;
-                nr[4] = (z + 1u == L) ? y : r + L;
-                nr[5] = (z == 0u) ? r + lg.rows - L : r - L;
-                ncol[2] = ncol[3] = ncol[4] = ncol[5] = x;
-            }
-            bool local[2 * DIM], elig[2 * DIM];
-            uint32_t ba[2 * DIM];
-#pragma unroll
-            for (int m = 0; m < 2 * DIM; ++m) {
-                nb[m] = ncol[m] + nr[m] * L;
-                local[m] = nr[m] >= r0 && nr[m] < r0 + nrows;
-                ba[m] = local[m] ? slab_bit(lg, ncol[m], nr[m], r0) : 0u;
-                // a local neighbour is a candidate only if its spin is s0; a
-                // remote one is decided by its owner
-                elig[m] = active && (!local[m] || bit_of(bits, ba[m]) == b0);
-            }
-            // bond words, drawn only where a lane of the wave needs them: one
-            // block keyed by j for the +mu bonds, one keyed by j - e_mu per -mu bond
-            uint32_t rp[3] = {0u, 0u, 0u}, rm[3] = {0u, 0u, 0u};
-            if (elig[0] || elig[2] || (DIM == 3 && elig[2 * DIM - 2])) {
-                const U4 w4 = philox(j, t, s, DOMAIN_BOND, k0, k1);
-                rp[0] = w4.x;
-                rp[1] = w4.y;
-                rp[2] = w4.z;
-            }
-#pragma unroll
-            for (int mu = 0; mu < DIM; ++mu) {
-                if (elig[2 * mu + 1]) {
-                    const U4 w4 = philox(nb[2 * mu + 1], t, s, DOMAIN_BOND, k0, k1);
-                    rm[mu] = (mu == 0) ? w4.x : (mu == 1) ? w4.y : w4.z;
+            if (avail <= BOND_SITES) {
+                const uint32_t si = tid / (uint32_t)D2;
+                const uint32_t m = tid - si * (uint32_t)D2;
+                const uint32_t nproc = min(avail, BOND_SITES);
+                const bool active = si < nproc;
+                const uint32_t j = active ? q[(head + si) & a.qmask] : 0u;
+                head += nproc;
+                uint32_t nr, nc;
+                lds_neighbour<DIM>(lg, j, m, nr, nc);
+                const uint32_t nbk = nc + nr * L;
+                const bool local = nr >= r0 && nr < r0 + nrows;
+                const uint32_t ba = local ? slab_bit(lg, nc, nr, r0) : 0u;
+                const bool elig = active && (!local || bit_of(bits, ba) == b0);
+                uint32_t rr = 0xFFFFFFFFu;
+                if (elig) {
+                    // bond (j, mu) for a +mu slot, (j - e_mu, mu) for a -mu slot
+                    const U4 w4 = philox((m & 1u) ? nbk : j, t, s, DOMAIN_BOND, k0, k1);
+                    const uint32_t mu = m >> 1;
+                    rr = (mu == 0u) ? w4.x : (mu == 1u) ? w4.y : w4.z;
                 }
-            }
-            bool won[2 * DIM], snd[2 * DIM];
+                const bool act = elig && rr < thr;
+                const bool won[1] = {act && local && claim_bit(bits, ba, b0)};
+                const bool snd[1] = {act && !local};
+                const bool to_next[1] = {(m & 1u) == 0u};
+                const uint32_t nb1[1] = {nbk};
+                lds_publish<WG, 1>(a, ctl, q, wave_cnt, wave_snd, sh, ov, won, snd, to_next, nb1, nproc,
+                                   epoch, b0, gprev, gnext, G, QC, head, tail, ovn, claims);
+            } else {
+                const uint32_t nproc = min(avail, (uint32_t)WG);
+                const bool active = tid < nproc;
+                const uint32_t j = active ? q[(head + tid) & a.qmask] : 0u;
+                head += nproc;
+                uint32_t nb[D2], ba[D2];
+                bool local[D2], elig[D2];
 #pragma unroll
-            for (int m = 0; m < 2 * DIM; ++m) {
-                const uint32_t rr = (m & 1) ? rm[m / 2] : rp[m / 2];
-                const bool act = elig[m] && rr < thr;
-                won[m] = act && local[m] && claim_bit(bits, ba[m], b0);
-                snd[m] = act && !local[m];
-            }
-            // compaction: claimed sites, and messages to the previous / next slab
-            uint32_t pos[2 * DIM], spos[2 * DIM];
-            const uint32_t wtot = wave_compact<DIM>(won, pos);
-            uint32_t sprev = 0u, snext = 0u;
+                for (int m = 0; m < D2; ++m) {
+                    uint32_t nr, nc;
+                    lds_neighbour<DIM>(lg, j, (uint32_t)m, nr, nc);
+                    nb[m] = nc + nr * L;
+                    local[m] = nr >= r0 && nr < r0 + nrows;
+                    ba[m] = local[m] ? slab_bit(lg, nc, nr, r0) : 0u;
+                    // a local neighbour is a candidate only if its spin is s0; a
+                    // remote one is decided by its owner
+                    elig[m] = active && (!local[m] || bit_of(bits, ba[m]) == b0);
+                }
+                // bond words, drawn only where a lane of the wave needs them: one
+                // block keyed by j for the +mu bonds, one keyed by j - e_mu per -mu bond
+                uint32_t rp[3] = {0u, 0u, 0u}, rm[3] = {0u, 0u, 0u};
+                if (elig[0] || elig[2] || (DIM == 3 && elig[D2 - 2])) {
+                    const U4 w4 = philox(j, t, s, DOMAIN_BOND, k0, k1);
+                    rp[0] = w4.x;
+                    rp[1] = w4.y;
+                    rp[2] = w4.z;
+                }
 #pragma unroll
-            for (int m = 0; m < 2 * DIM; ++m) {
-                // the slab of a remote neighbour: +y / +z go to the next slab, -y / -z to the previous
-                const bool to_next = (m & 1) == 0;
-                const uint64_t mp = __ballot(snd[m] && !to_next);
-                const uint64_t mn = __ballot(snd[m] && to_next);
-                spos[m] = to_next ? snext + lane_prefix(mn) : sprev + lane_prefix(mp);
-                sprev += (uint32_t)__popcll(mp);
-                snext += (uint32_t)__popcll(mn);
-            }
-            if (lane == 0) {
-                wave_cnt[wv] = wtot;
-                wave_snd[wv] = sprev;
-                wave_snd[NW + wv] = snext;
-            }
-            __syncthreads();
-            uint32_t before = 0u, total = 0u, pb = 0u, ptot = 0u, nbf = 0u, ntot = 0u;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                const uint32_t c = wave_cnt[w], cp = wave_snd[w], cn = wave_snd[NW + w];
-                const bool lower = (uint32_t)w < wv;
-                before += lower ? c : 0u;
-                pb += lower ? cp : 0u;
-                nbf += lower ? cn : 0u;
-                total += c;
-                ptot += cp;
-                ntot += cn;
-            }
-            if (G > 1u) {
-                if (tid == 0) {
-                    const long long delta = (long long)total + (long long)(ptot + ntot) - (long long)nproc;
-                    if (ptot + ntot > 0u) {
-                        // the units of the messages must be in P before a
-                        // receiver can consume them: wait for the addition
-                        sh[7] = (uint32_t)__hip_atomic_fetch_add(&ctl->P, (unsigned long long)delta,
-                                                                 __ATOMIC_RELAXED, SCOPE_AGENT);
-                        sh[5] = ptot ? __hip_atomic_fetch_add(&a.inbox_tail[gprev], ptot, __ATOMIC_RELAXED, SCOPE_AGENT) : 0u;
-                        sh[6] = ntot ? __hip_atomic_fetch_add(&a.inbox_tail[gnext], ntot, __ATOMIC_RELAXED, SCOPE_AGENT) : 0u;
-                    } else if (delta != 0) {
-                        __hip_atomic_fetch_add(&ctl->P, (unsigned long long)delta, __ATOMIC_RELAXED, SCOPE_AGENT);
+                for (int mu = 0; mu < DIM; ++mu) {
+                    if (elig[2 * mu + 1]) {
+                        const U4 w4 = philox(nb[2 * mu + 1], t, s, DOMAIN_BOND, k0, k1);
+                        rm[mu] = (mu == 0) ? w4.x : (mu == 1) ? w4.y : w4.z;
                     }
                 }
-                if (ptot + ntot > 0u) {
-                    __syncthreads();
-                    const uint32_t basep = sh[5], basen = sh[6];
-                    const unsigned long long word = epoch | (b0 ? MSG_S0_NEG : 0u);
+                bool act[D2], won[D2], snd[D2], to_next[D2];
 #pragma unroll
-                    for (int m = 0; m < 2 * DIM; ++m) {
-                        if (snd[m]) {
-                            const bool to_next = (m & 1) == 0;
-                            const uint32_t dst = to_next ? gnext : gprev;
-                            const uint32_t slot = to_next ? basen + nbf + spos[m] : basep + pb + spos[m];
-                            __hip_atomic_store(&a.inbox[(size_t)dst * (a.imask + 1u) + (slot & a.imask)],
-                                               word | nb[m], __ATOMIC_RELAXED, SCOPE_AGENT);
-                        }
-                    }
+                for (int m = 0; m < D2; ++m) {
+                    const uint32_t rr = (m & 1) ? rm[m / 2] : rp[m / 2];
+                    act[m] = elig[m] && rr < thr && local[m];
+                    snd[m] = elig[m] && rr < thr && !local[m];
+                    to_next[m] = (m & 1) == 0;
                 }
+                // every claim's LDS atomic in flight at once
+                claim_bits<D2>(bits, ba, act, b0, won);
+                lds_publish<WG, D2>(a, ctl, q, wave_cnt, wave_snd, sh, ov, won, snd, to_next, nb, nproc,
+                                    epoch, b0, gprev, gnext, G, QC, head, tail, ovn, claims);
             }
-            // append the claimed sites to the ring (or the overflow stack)
-            if (total <= QC - (tail - head)) {
-#pragma unroll
-                for (int m = 0; m < 2 * DIM; ++m)
-                    if (won[m]) q[(tail + before + pos[m]) & a.qmask] = nb[m];
-                tail += total;
-            } else {
-#pragma unroll
-                for (int m = 0; m < 2 * DIM; ++m)
-                    if (won[m]) ov[ovn + before + pos[m]] = nb[m];
-                ovn += total;
-            }
-            claims += total;
             if (look && tid == 0) sh[3] = it_async;
             __syncthreads();
         }
@@ -587,13 +694,34 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
             red[NW + wv] = nsum;
         }
         __syncthreads();
-        if (tid == 0) {
-            uint64_t sd = 0u, sn = 0u;
-            for (int w = 0; w < NW; ++w) {
-                sd += red[w];
-                sn += red[NW + w];
+        if (G == 1u) {
+            // one workgroup: thread 0 keeps M and B in registers and writes
+            // the record; the stop request was read at the update's start
+            if (tid == 0) {
+                uint64_t sd = 0u, sn = 0u;
+                for (int w = 0; w < NW; ++w) {
+                    sd += red[w];
+                    sn += red[NW + w];
+                }
+                M1 += (b0 ? 2ll : -2ll) * (long long)claims;          // M -= 2 s0 |C|
+                if (measure) {
+                    B1 = (int64_t)DIM * (int64_t)lg.N - 2 * (int64_t)sd;
+                    if ((int64_t)lg.N - 2 * (int64_t)sn != M1) err1 |= ERR_MAG;
+                }
+                wolff_record rr;
+                rr.bond_sum = measure ? B1 : (int64_t)WOLFF_NOT_MEASURED;
+                rr.mag = M1;
+                rr.csize = (int64_t)claims;
+                R->rec[rec0 + done] = rr;
+                sh[5] = abort_now | (err1 != 0u ? 1u : 0u);
             }
-            if (G > 1u) {
+        } else {
+            if (tid == 0) {
+                uint64_t sd = 0u, sn = 0u;
+                for (int w = 0; w < NW; ++w) {
+                    sd += red[w];
+                    sn += red[NW + w];
+                }
                 if (measure) {
                     __hip_atomic_fetch_add(&ctl->acc_diff, (unsigned long long)sd, __ATOMIC_RELAXED, SCOPE_AGENT);
                     __hip_atomic_fetch_add(&ctl->acc_neg, (unsigned long long)sn, __ATOMIC_RELAXED, SCOPE_AGENT);
@@ -604,41 +732,36 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
                     __hip_atomic_fetch_add(&ctl->acc_claims, (unsigned long long)claims, __ATOMIC_RELAXED, SCOPE_AGENT);
                     __hip_atomic_fetch_add(&ctl->acc_dm, (unsigned long long)dm, __ATOMIC_RELAXED, SCOPE_AGENT);
                 }
-            } else {
-                ctl->acc_diff = sd;
-                ctl->acc_neg = sn;
-                ctl->acc_claims = claims;
-                ctl->acc_dm = (unsigned long long)((b0 ? 2ll : -2ll) * (long long)claims);
             }
+            grid_barrier(ctl, G, [&] {
+                // the last workgroup: |C|, M exactly (M -= 2 s0 |C|, summed over
+                // the slabs that claimed), B and the M recount, the record, and
+                // the stop request
+                const unsigned long long csize = ld_agent(&ctl->acc_claims);
+                const int64_t M = ctl->M + (int64_t)ld_agent(&ctl->acc_dm);
+                int64_t B = ctl->B;
+                if (measure) {
+                    B = (int64_t)DIM * (int64_t)lg.N - 2 * (int64_t)ld_agent(&ctl->acc_diff);
+                    const int64_t Mm = (int64_t)lg.N - 2 * (int64_t)ld_agent(&ctl->acc_neg);
+                    if (Mm != M) ctl->err |= ERR_MAG;
+                }
+                ctl->M = M;
+                ctl->B = B;
+                wolff_record rr;
+                rr.bond_sum = measure ? B : (int64_t)WOLFF_NOT_MEASURED;
+                rr.mag = M;
+                rr.csize = (int64_t)csize;
+                R->rec[rec0 + done] = rr;
+                __hip_atomic_store(&ctl->acc_diff, 0ull, __ATOMIC_RELAXED, SCOPE_AGENT);
+                __hip_atomic_store(&ctl->acc_neg, 0ull, __ATOMIC_RELAXED, SCOPE_AGENT);
+                __hip_atomic_store(&ctl->acc_claims, 0ull, __ATOMIC_RELAXED, SCOPE_AGENT);
+                __hip_atomic_store(&ctl->acc_dm, 0ull, __ATOMIC_RELAXED, SCOPE_AGENT);
+                const uint32_t failed = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, SCOPE_AGENT) != 0u;
+                __hip_atomic_store(&ctl->stop, abort_requested(abort_flag) | (failed ? 1u : 0u),
+                                   __ATOMIC_RELAXED, SCOPE_AGENT);
+            });
+            if (tid == 0) sh[5] = __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, SCOPE_AGENT);
         }
-        grid_barrier(ctl, G, [&] {
-            // the last workgroup: |C|, M exactly (M -= 2 s0 |C|, summed over
-            // the slabs that claimed), B and the M recount, the record, and
-            // the stop request
-            const unsigned long long csize = ld_agent(&ctl->acc_claims);
-            const int64_t M = ctl->M + (int64_t)ld_agent(&ctl->acc_dm);
-            int64_t B = ctl->B;
-            if (measure) {
-                B = (int64_t)DIM * (int64_t)lg.N - 2 * (int64_t)ld_agent(&ctl->acc_diff);
-                const int64_t Mm = (int64_t)lg.N - 2 * (int64_t)ld_agent(&ctl->acc_neg);
-                if (Mm != M) ctl->err |= ERR_MAG;
-            }
-            ctl->M = M;
-            ctl->B = B;
-            wolff_record rr;
-            rr.bond_sum = measure ? B : (int64_t)WOLFF_NOT_MEASURED;
-            rr.mag = M;
-            rr.csize = (int64_t)csize;
-            R->rec[rec0 + done] = rr;
-            __hip_atomic_store(&ctl->acc_diff, 0ull, __ATOMIC_RELAXED, SCOPE_AGENT);
-            __hip_atomic_store(&ctl->acc_neg, 0ull, __ATOMIC_RELAXED, SCOPE_AGENT);
-            __hip_atomic_store(&ctl->acc_claims, 0ull, __ATOMIC_RELAXED, SCOPE_AGENT);
-            __hip_atomic_store(&ctl->acc_dm, 0ull, __ATOMIC_RELAXED, SCOPE_AGENT);
-            const uint32_t failed = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, SCOPE_AGENT) != 0u;
-            __hip_atomic_store(&ctl->stop, abort_requested(R->abort) | (failed ? 1u : 0u),
-                               __ATOMIC_RELAXED, SCOPE_AGENT);
-        });
-        if (tid == 0) sh[5] = __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, SCOPE_AGENT);
         __syncthreads();
         const uint32_t stop = sh[5];
         __syncthreads();
@@ -660,6 +783,11 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
             const uint32_t addr = (DIM == 2) ? site_addr<2>(geo, j) : site_addr<3>(geo, j);
             SW[addr] = ((v >> b) & 1u) ? (int8_t)-1 : (int8_t)1;
         }
+    }
+    if (G == 1u && tid == 0) {
+        ctl->M = M1;
+        ctl->B = B1;
+        ctl->err |= err1;
     }
     grid_barrier(ctl, G, [&] {
         R->t = t0 + done;

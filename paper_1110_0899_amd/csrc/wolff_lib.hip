@@ -439,9 +439,13 @@ static bool lds_plan(int dim, uint32_t L, uint32_t slab_bits, LdsPlan* out)
 
 using LdsFn = void (*)(wolff::LdsArgs, uint32_t);
 
-static LdsFn lds_fn(int wg, int dim)
+// The LDS-path kernel for a workgroup size, a dimension and a slab count
+// (one slab: the single-workgroup instance).
+static LdsFn lds_fn(int wg, int dim, uint32_t G)
 {
-#define WOLFF_PICK_LDS(W) return dim == 2 ? wolff::lds_kernel<W, 2> : wolff::lds_kernel<W, 3>
+#define WOLFF_PICK_LDS(W)                                                               \
+    if (G > 1u) return dim == 2 ? wolff::lds_kernel<W, 2, true> : wolff::lds_kernel<W, 3, true>; \
+    return dim == 2 ? wolff::lds_kernel<W, 2, false> : wolff::lds_kernel<W, 3, false>
     switch (wg) {
     case 64: WOLFF_PICK_LDS(64);
     case 128: WOLFF_PICK_LDS(128);
@@ -807,7 +811,7 @@ static int ensure_lds(wolff_sim* s, const LdsPlan& p)
     HIP_TRY(hipMalloc(&s->ltail, s->lbytes_tail));
     HIP_TRY(hipMalloc(&s->lbnd, (size_t)G * p.bnd_words * sizeof(uint32_t)));
     HIP_TRY(hipMalloc(&s->lov, (size_t)G * p.ov_stride * sizeof(uint32_t)));
-    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(lds_fn(p.wg, s->dim)),
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(lds_fn(p.wg, s->dim, p.lg.G)),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes));
     return lds_reset(s);
 }
@@ -836,7 +840,7 @@ static int run_lds(wolff_sim* s, uint64_t n)
     const double cl = s->csize_mean >= 0.0 ? s->csize_mean : (double)s->N;
     const double work = cl + (double)s->N / 64.0 + 64.0;
     const uint64_t chunk = (uint64_t)std::max(1.0, std::min(65536.0, (double)(1ull << 27) / work));
-    const LdsFn fn = lds_fn(p.wg, s->dim);
+    const LdsFn fn = lds_fn(p.wg, s->dim, p.lg.G);
     for (uint64_t done = 0; done < n;) {
         const uint32_t m = (uint32_t)std::min<uint64_t>(chunk, n - done);
         EventPair ev{};
