@@ -582,10 +582,13 @@ def main():
             leg["kernel_frac_of_measured_copy"] = leg["kernel_GBs_algorithmic"] / copy_gbs
 
     achieved = main_leg["grow_GBs_algorithmic"]
-    team = main_leg["path"] == binding.PATH_TEAM
-    kernel = "team_kernel" if team else "batch_kernel"
-    # the committed counters are the team kernel's at this workload
-    traffic = counter_traffic("team_kernel", "2d_L4096") if team else None
+    kernel, path_desc = {
+        binding.PATH_TEAM: ("team_kernel", "multi-workgroup team kernel"),
+        binding.PATH_LDS: ("lds_kernel", "LDS-resident lattice, 16 slabs of 256 rows"),
+        binding.PATH_SINGLE: ("batch_kernel", "one-workgroup kernel"),
+    }[main_leg["path"]]
+    # committed counters of that kernel at this workload, if taken on the current sources
+    traffic = counter_traffic(kernel, "2d_L4096")
     out = {
         "metric": "added spins/s at Tc, 2D L=4096 & 3D L=256; % HBM peak; batched vs plain",
         "value": main_leg["added_per_s"],
@@ -605,8 +608,7 @@ def main():
             "start": "ordered, thermalised at T_c before the timed updates",
             "thermalisation_updates": main_leg["warmup"],
             "mean_cluster_size_last_thermalisation": main_leg["therm_mean_csize"],
-            "path": ("plain one-lattice launch path (multi-workgroup team kernel)" if team
-                     else "plain one-lattice launch path (one-workgroup kernel)"),
+            "path": "plain one-lattice launch path (%s)" % path_desc,
             "measurement": "E and M after every update",
             "mean_cluster_size": main_leg["mean_csize"],
             "updates_per_s": main_leg["updates_per_s"],

@@ -263,14 +263,16 @@ int wolff_set_stream(wolff_sim *s, void *hip_stream);
  * WOLFF_PATH_SINGLE runs every update in one workgroup (LDS
  * frontier queue, one launch for many updates); WOLFF_PATH_TEAM runs each
  * update on `workgroups` cooperating workgroups (0 = library default) that
- * share an atomic-counter frontier.  WOLFF_PATH_AUTO takes the path with
- * the lower estimated cost per update, from the mean cluster size of the
+ * share an atomic-counter frontier.  WOLFF_PATH_AUTO takes the LDS path
+ * for Ising lattices it holds in one workgroup, and for those of at least
+ * 2^22 sites it holds at all; otherwise the path with the lower estimated
+ * cost per update of the other two, from the mean cluster size of the
  * latest records (at most 256) returned by wolff_observables, the lattice
  * size and the measurement mode (both costs grow with the cluster's
  * breadth-first depth; one workgroup adds a cost per site and its lattice
  * recount).  Before any records are returned (and after wolff_set_spins)
- * it takes the single path for lattices under 2^20 sites, the team path
- * otherwise.  Every path gives the same records and spins. */
+ * that choice takes the single path for lattices under 2^20 sites, the
+ * team path otherwise.  Every path gives the same records and spins. */
 #define WOLFF_PATH_AUTO   0
 #define WOLFF_PATH_SINGLE 1
 #define WOLFF_PATH_TEAM   2

@@ -462,9 +462,24 @@ static bool lds_fits(const wolff_sim* s)
            (int)p.lg.G <= device_cus();
 }
 
+// Ising lattices the LDS path holds in one workgroup, or in several when
+// the lattice has at least 2^22 sites: there it was the fastest path at
+// every measured size and temperature window on MI355X (square lattices
+// L = 32 ... 4096 and simple-cubic L = 32, 64, 256 at their critical
+// points, 1.2x to 1.5x the best of the other two).  A lattice split over a
+// few slabs (simple-cubic L = 128 on two) was slower than one workgroup,
+// so smaller split lattices stay with the cost model below.
+static bool lds_preferred(const wolff_sim* s)
+{
+    LdsPlan p;
+    if (!lds_fits(s) || !lds_plan(s->dim, (uint32_t)s->L, s->lds_slab_bits, &p)) return false;
+    return p.lg.G == 1u || s->N >= (1ull << 22);
+}
+
 static int resolved_path(const wolff_sim* s)
 {
     if (s->path != WOLFF_PATH_AUTO) return s->path;
+    if (lds_preferred(s)) return WOLFF_PATH_LDS;
     if (s->csize_mean < 0.0)      // no records yet: by lattice size
         return s->N < (1ull << 20) ? WOLFF_PATH_SINGLE : WOLFF_PATH_TEAM;
     return single_cost_us(s) <= team_cost_us(s) ? WOLFF_PATH_SINGLE : WOLFF_PATH_TEAM;

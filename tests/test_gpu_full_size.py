@@ -27,12 +27,15 @@ def gpu():
 
 
 @pytest.mark.parametrize("dim,L,T,seed", SIZES)
-def test_plain_full_size_sampled(dim, L, T, seed):
-    print("case full-size plain dim=%d L=%d" % (dim, L), flush=True)
+def test_team_full_size_sampled(dim, L, T, seed):
+    print("case full-size team dim=%d L=%d" % (dim, L), flush=True)
     thr = oracle.threshold(1.0, T)
     N = L ** dim
-    with binding.Simulation(dim, L, 1.0, T, seed) as sim:       # default path: the team kernel
-        assert sim.info().path == binding.PATH_TEAM
+    with binding.Simulation(dim, L, 1.0, T, seed) as sim:
+        # the default at these sizes is the LDS path (its full-size windows
+        # are in test_gpu_lds.py); here the multi-workgroup team kernel
+        assert sim.info().path == binding.PATH_LDS
+        sim.set_path(binding.PATH_TEAM)
         sim.run(8)
         got = as_array(sim.observables())
         S = oracle.init_spins(dim, L, seed)

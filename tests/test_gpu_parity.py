@@ -352,13 +352,18 @@ def test_auto_path_follows_cost():
 
 def test_auto_path_picks_one_workgroup_for_mid_size_clusters():
     # square lattice L = 1024 at T_c with measurement, from the ordered
-    # state: once the clusters have relaxed to a few 1e5 sites (updates
-    # 20 to 40 of this seed), one workgroup is the cheaper path
+    # state, its LDS slabs lowered so that the lattice would take 16 of
+    # them (2^20 sites, below the size from which AUTO takes a split LDS
+    # lattice): the cost model chooses between the other two paths, and
+    # once the clusters have relaxed to a few 1e5 sites (updates 20 to 40
+    # of this seed) one workgroup is the cheaper one
     dim, L, T, seed = 2, 1024, TC2, 31
     thr = oracle.threshold(1.0, T)
     S = np.ones(L * L, dtype=np.int8)
     ref = oracle.run(dim, L, thr, seed, 0, 60, S)
     with binding.Simulation(dim, L, 1.0, T, seed) as sim:
+        assert sim.info().path == binding.PATH_LDS           # one slab: the LDS path
+        sim.set_lds_slab(1 << 16)
         sim.set_spins(np.ones(L * L, dtype=np.int8), 0)
         assert sim.info().path == binding.PATH_TEAM
         parts = []
