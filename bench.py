@@ -240,20 +240,32 @@ def c4_leg(binding, workloads, n_updates):
     # grown; an early window (clusters still small) favours small workgroups
     # (128 threads: 17.7 s against 10.4 s with 256 over the whole run).
     tuned = autotune.tune(workloads.c4_jobs(2400), warm=2000, timed=400, start=0, log=log)
-    b = binding.Batch(jobs, start=0)
-    b.set_tiles(tuned["wg"], tuned["queue_entries"])
-    b.set_measure(True)
-    a = time.perf_counter()
-    b.run()
-    ms = b.last_ms()
-    wall = time.perf_counter() - a
-    added = sum(int(b.records(i)["csize"].sum()) for i in range(len(jobs)))
-    b.close()
-    log("C4: %d replicas x %d updates, makespan %.2f s (kernel %.2f s), %.3e added/s"
-        % (len(jobs), n_updates, wall, ms * 1e-3, added / wall))
+    def run(lds):
+        b = binding.Batch(jobs, start=0)
+        b.set_tiles(tuned["wg"], tuned["queue_entries"])
+        b.set_measure(True)
+        b.set_lds(lds)
+        a = time.perf_counter()
+        b.run()
+        ms = b.last_ms()
+        wall = time.perf_counter() - a
+        added = sum(int(b.records(i)["csize"].sum()) for i in range(len(jobs)))
+        b.close()
+        return wall, ms, added
+
+    # the replicas that fit one workgroup's LDS run on the batched LDS path;
+    # the same set all on the one-workgroup kernel, for comparison
+    wall, ms, added = run(True)
+    wall_g, ms_g, added_g = run(False)
+    assert added_g == added
+    n_lds = sum(1 for j in jobs if (32 * -(-j.L // 32)) * j.L ** (j.dim - 1) <= (1 << 20))
+    log("C4: %d replicas x %d updates (%d on the LDS path), makespan %.2f s (kernel %.2f s), "
+        "%.3e added/s; all on the one-workgroup kernel: %.2f s"
+        % (len(jobs), n_updates, n_lds, wall, ms * 1e-3, added / wall, wall_g))
     return {"replicas": len(jobs), "updates_each": n_updates, "makespan_s": wall,
             "kernel_s": ms * 1e-3, "added": added, "added_per_s": added / wall,
             "cluster_updates_per_s": len(jobs) * n_updates / wall,
+            "replicas_on_lds_path": n_lds, "makespan_one_workgroup_kernel_s": wall_g,
             "wg": tuned["wg"], "queue_entries": tuned["queue_entries"]}
 
 
@@ -441,6 +453,77 @@ def cpu_baseline(leg, budget_s=15.0):
     }
 
 
+def stats_counts(binding, workloads):
+    """Counting build (libwolff_stats.so, loaded with WOLFF_LIBRARY=stats):
+    the work and the global-memory bytes each hot kernel issues per added
+    spin, on the benchmarked states: the headline lattice and the cubic
+    L = 256 lattice thermalised on the default (LDS) path and on the team
+    path, and 64 replicas of the batched form of each."""
+    out = {}
+
+    def per_spin(c):
+        sites = max(c["sites"], 1)
+        touched = c["read_bytes"] + c["write_bytes"] + c["atomic_bytes"]
+        return {"counters": c, "bytes_touched_per_added_spin": touched / sites,
+                "read_bytes_per_added_spin": c["read_bytes"] / sites,
+                "write_bytes_per_added_spin": c["write_bytes"] / sites,
+                "atomic_bytes_per_added_spin": c["atomic_bytes"] / sites,
+                "philox_blocks_per_added_spin": c["philox"] / sites,
+                "steps_per_update": c["steps"] / max(c["updates"], 1),
+                "messages_per_added_spin": c["messages"] / sites}
+
+    for dim, L, T, seed, warm, n in [(2, 4096, workloads.TC_2D, 2, 1000, 40),
+                                     (3, 256, workloads.T_3D, 3, 3000, 200)]:
+        for name, path in (("default", None), ("team", binding.PATH_TEAM)):
+            sim = binding.Simulation(dim, L, 1.0, T, seed)
+            sim.set_spins(ordered_start(L ** dim), 0)
+            sim.run(warm)
+            sim.synchronize()
+            sim.observables()
+            if path is not None:
+                sim.set_path(path)
+            sim.stats(reset=True)
+            sim.run(n)
+            sim.synchronize()
+            rec = sim.observables()
+            c = sim.stats()
+            path_used = int(sim.info().path)
+            sim.close()
+            r = per_spin(c)
+            r["path"] = path_used
+            r["updates"] = n
+            r["added"] = int(rec["csize"].sum())
+            out["%dd_L%d_%s" % (dim, L, name)] = r
+            log("stats %dD L=%d %s (path %d): %.1f B touched / added spin, %.2f Philox blocks, "
+                "%.0f steps / update" % (dim, L, name, path_used, r["bytes_touched_per_added_spin"],
+                                         r["philox_blocks_per_added_spin"], r["steps_per_update"]))
+    for dim, L, warm, n in [(2, 4096, 100, 8), (3, 256, 1000, 40)]:
+        jobs = workloads.same_shape_jobs(dim, L, 64, warm + n)
+        b = binding.Batch(jobs, start=1)
+        b.run(warm)
+        b.last_ms()
+        b.stats(reset=True)
+        b.run(n)
+        c = b.stats()
+        b.close()
+        r = per_spin(c)
+        out["batch_%dd_L%d_x64" % (dim, L)] = r
+        log("stats batch %dD L=%d x64: %.1f B touched / added spin" % (dim, L, r["bytes_touched_per_added_spin"]))
+    return out
+
+
+def stats_leg():
+    """stats_counts in a child process that loads the counting build."""
+    import subprocess
+    env = dict(os.environ, WOLFF_LIBRARY="stats")
+    p = subprocess.run([sys.executable, os.path.abspath(__file__), "--profile-leg", "stats"],
+                       env=env, capture_output=True, text=True)
+    sys.stderr.write(p.stderr[-4000:])
+    if p.returncode != 0:
+        return {"error": "counting build run failed (rc %d)" % p.returncode}
+    return json.loads(p.stdout.strip().splitlines()[-1])
+
+
 def profile_only(args, binding, workloads):
     """One leg alone, for rocprofv3 runs (kernel trace or counters)."""
     import torch
@@ -461,6 +544,8 @@ def profile_only(args, binding, workloads):
                            else (3, 256, workloads.T_3D, 3))
         r = plain_leg(binding, dim, L, T, seed, max(args.warmup, MIN_THERM[dim]), args.steps,
                       path=path)
+    elif leg == "stats":
+        r = stats_counts(binding, workloads)
     elif leg in ("batch2d", "batch3d"):
         wg, q = (int(v) for v in args.tiles.split(","))
         dim, L = (2, 4096) if leg == "batch2d" else (3, 256)
@@ -478,7 +563,7 @@ def build_parser() -> argparse.ArgumentParser:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000, help="timed updates of the headline leg")
     ap.add_argument("--warmup", type=int, default=1000, help="thermalisation updates")
-    ap.add_argument("--legs", default="plain2d,plain3d,updateonly,c1,batch2d,batch3d,c4,serve")
+    ap.add_argument("--legs", default="plain2d,plain3d,updateonly,c1,batch2d,batch3d,c4,serve,stats")
     ap.add_argument("--c4-updates", type=int, default=10000,
                     help="updates per replica of the mixed C4 batch")
     ap.add_argument("--batch-replicas", type=int, default=2048)
@@ -494,9 +579,10 @@ def build_parser() -> argparse.ArgumentParser:
     ap.add_argument("--path", default="auto", choices=("auto", "single", "team", "lds"),
                     help="growth path of a profiled plain leg (default: the library's choice)")
     ap.add_argument("--profile-leg", default=None,
-                    choices=("plain2d", "plain3d", "batch2d", "batch3d", "copy"),
+                    choices=("plain2d", "plain3d", "batch2d", "batch3d", "copy", "stats"),
                     help="run only this leg (plain2d, plain3d, batch2d, batch3d, copy) for a "
-                         "profiler; prints that leg's numbers instead of the benchmark line")
+                         "profiler, or the counting-build leg (stats, with WOLFF_LIBRARY=stats); "
+                         "prints that leg's numbers instead of the benchmark line")
     return ap
 
 
@@ -575,6 +661,8 @@ def main():
         extra["c4_mixed_batch"] = c4_leg(binding, workloads, args.c4_updates)
     if "serve" in legs:
         extra["serve_stream"] = serve_leg(binding, workloads)
+    if "stats" in legs:
+        extra["counting_build"] = stats_leg()
     copy_gbs = copy_peak_gbs()
     log("device copy: %.0f GB/s" % copy_gbs)
     for leg in extra.values():

@@ -293,6 +293,12 @@ int wolff_set_tiles(wolff_sim *s, int wg, int queue_entries);
  * workgroups (the paper's blocks, Section 4).  WOLFF_EINVAL otherwise. */
 int wolff_set_lds_slab(wolff_sim *s, uint32_t slab_bits);
 
+/* LDS-resident path: threads per workgroup (the paper's block size,
+ * Section 4), 64, 128, 256, 512 or 1024; 0 restores the default (256 for
+ * a lattice on several slabs; on one slab 64 up to 4096 spins, 128 up to
+ * 16384, 256 below 2^18, 512 above).  WOLFF_EINVAL otherwise. */
+int wolff_set_lds_tiles(wolff_sim *s, int wg);
+
 /* Team path: replay a captured HIP graph of `chunk` updates (step (v) of
  * Section 2 repeated on the device without host launches; the seed,
  * growth and measurement launches of each) instead of launching them one by
@@ -308,6 +314,32 @@ int wolff_set_graph(wolff_sim *s, int chunk);
 int wolff_profile(wolff_sim *s, int on);
 int wolff_profile_read(wolff_sim *s, double *grow_ms, uint64_t *grow_launches,
                        double *measure_ms, uint64_t *measure_launches);
+
+/* Counting build (the library built with -DWOLFF_STATS=1, libwolff_stats.so):
+ * the kernels count, per lattice, the work and the global memory accesses
+ * they issue (Section 6 names the random, uncoalesced global accesses of
+ * the growth as its bottleneck; these counters measure them).  Bytes are
+ * those of the accesses issued (the access width times the count), not the
+ * DRAM traffic, which caches reduce.  wolff_stats_read waits for the
+ * handle's stream, copies min(n, WOLFF_STAT_COUNT) counters to out (summed
+ * since creation or the last reset) and, with reset != 0, zeroes them.
+ * WOLFF_EINVAL in the normal build. */
+#define WOLFF_STAT_UPDATES         0  /* updates run                                    */
+#define WOLFF_STAT_SITES           1  /* frontier sites expanded (the sum of |C|)       */
+#define WOLFF_STAT_STEPS           2  /* growth steps, summed over workgroups           */
+#define WOLFF_STAT_STEPS_NARROW    3  /* LDS path: steps with one lane per bond         */
+#define WOLFF_STAT_NEIGHBOUR_READS 4  /* neighbour spin reads (global or LDS)           */
+#define WOLFF_STAT_PHILOX          5  /* Philox4x32-10 blocks computed for live lanes   */
+#define WOLFF_STAT_CLAIMS          6  /* claim operations issued                        */
+#define WOLFF_STAT_READ_BYTES      7  /* global memory bytes read                       */
+#define WOLFF_STAT_WRITE_BYTES     8  /* global memory bytes written                    */
+#define WOLFF_STAT_ATOMIC_BYTES    9  /* global memory atomics (operand bytes)          */
+#define WOLFF_STAT_MESSAGES       10  /* LDS path: messages to another slab             */
+#define WOLFF_STAT_IDLE_POLLS     11  /* polls of a workgroup waiting for work          */
+#define WOLFF_STAT_CYCLES_GROW    12  /* LDS path: thread-0 shader cycles in growth     */
+#define WOLFF_STAT_CYCLES_IDLE    13  /* LDS path: thread-0 shader cycles polling idle  */
+#define WOLFF_STAT_COUNT          16
+int wolff_stats_read(wolff_sim *s, uint64_t *out, int n, int reset);
 
 /* Static description of an error code (never NULL).  (Plumbing: no
  * passage of the paper.) */
@@ -386,10 +418,24 @@ int wolff_batch_set_stream(wolff_batch *b, void *hip_stream);
  * [wg, 8192] (queue and claim table, 8 entries per thread, 4 bytes each,
  * within 64 KiB of LDS); WOLFF_EINVAL otherwise. */
 int wolff_batch_set_tiles(wolff_batch *b, int wg, int queue_entries);
+/* Replicas of the Ising model whose lattice fits one workgroup's LDS (at
+ * most 2^20 bits with rows padded to a multiple of 32: square lattices up
+ * to L = 1024, simple-cubic up to L = 96) run on the LDS-resident path (as WOLFF_PATH_LDS with one slab:
+ * the lattice as bits in LDS for the whole launch), in two launches by LDS
+ * size that run concurrently with the one-workgroup launch of the other
+ * replicas (the batched form of Section 4's frontier growth, same records).
+ * on = 0 puts every replica on the one-workgroup kernel.  Default 1.
+ * Takes effect at the next wolff_batch_run.  (A launch configuration, not a
+ * passage of the paper.) */
+int wolff_batch_set_lds(wolff_batch *b, int on);
 
 /* Elapsed milliseconds of the last wolff_batch_run's kernel (HIP events on
  * the batch's stream; synchronises), and the number of launches it made. */
 int wolff_batch_last_ms(wolff_batch *b, double *ms);
+
+/* Counting build: the WOLFF_STAT_* counters (see wolff_stats_read) summed
+ * over every replica of the batch.  WOLFF_EINVAL in the normal build. */
+int wolff_batch_stats_read(wolff_batch *b, uint64_t *out, int n, int reset);
 
 /* ------------------------------------------------------------ serving loop */
 /* Serving form (not a passage of the paper: each job runs the update of
@@ -438,6 +484,14 @@ int wolff_server_submit(wolff_server *srv, const wolff_job *job, uint64_t *job_i
  * quantum is spent or it finishes), retire finished jobs.  Synchronous.
  * *n_finished receives the number of jobs that finished in this step. */
 int wolff_server_step(wolff_server *srv, double quantum_ms, uint64_t *n_finished);
+
+/* Run each quantum's jobs that fit one workgroup's LDS (Ising, at most 2^20
+ * bits with rows padded to 32) on the batched LDS path, as
+ * wolff_batch_set_lds does for a batch (as many as are resident at once;
+ * the rest and every other job on the one-workgroup kernel); on = 0: all
+ * on the one-workgroup kernel.  Default 1.  Records are the same either
+ * way.  (A launch configuration, not a passage of the paper.) */
+int wolff_server_set_lds(wolff_server *srv, int on);
 
 /* State (WOLFF_JOB_*) and updates done of one job. */
 int wolff_server_status(wolff_server *srv, uint64_t job_id, int *state, uint64_t *updates_done);

@@ -18,7 +18,11 @@ import numpy as np
 import torch  # noqa: F401  (one HIP runtime per process: torch's)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIBRARY = os.path.join(HERE, "libwolff.so")
+# WOLFF_LIBRARY=stats loads the counting build (libwolff_stats.so), any other
+# value is taken as a path; unset: libwolff.so
+_CHOICE = os.environ.get("WOLFF_LIBRARY", "")
+LIBRARY = (os.path.join(HERE, "libwolff_stats.so") if _CHOICE == "stats"
+           else _CHOICE or os.path.join(HERE, "libwolff.so"))
 
 OK, EINVAL, ENOMEM, EDEVICE, ERANGE, ESTATE, EABORTED = 0, -1, -2, -3, -4, -5, -6
 NOT_MEASURED = -(2 ** 63)
@@ -74,6 +78,12 @@ class ServerStats(ctypes.Structure):
 
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
+# WOLFF_STAT_* counters of the counting build, in index order
+STAT_NAMES = ["updates", "sites", "steps", "steps_narrow", "neighbour_reads", "philox", "claims",
+              "read_bytes", "write_bytes", "atomic_bytes", "messages", "idle_polls", "cycles_grow",
+              "cycles_idle"]
+STAT_COUNT = 16
+
 RECORD_DTYPE = np.dtype([("bond_sum", np.int64), ("mag", np.int64), ("csize", np.int64)])
 
 # name -> (restype, argtypes); every symbol declared in include/wolff.h
@@ -99,6 +109,7 @@ SIGNATURES = {
     "wolff_set_path": (_I, [_P, _I, _I]),
     "wolff_set_graph": (_I, [_P, _I]),
     "wolff_set_lds_slab": (_I, [_P, ctypes.c_uint32]),
+    "wolff_set_lds_tiles": (_I, [_P, _I]),
     "wolff_set_tiles": (_I, [_P, _I, _I]),
     "wolff_profile": (_I, [_P, _I]),
     "wolff_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_U64),
@@ -115,11 +126,15 @@ SIGNATURES = {
     "wolff_batch_set_stream": (_I, [_P, _P]),
     "wolff_batch_set_graph": (_I, [_P, _I]),
     "wolff_batch_set_tiles": (_I, [_P, _I, _I]),
+    "wolff_batch_set_lds": (_I, [_P, _I]),
     "wolff_batch_last_ms": (_I, [_P, ctypes.POINTER(_D)]),
+    "wolff_batch_stats_read": (_I, [_P, _P, _I, _I]),
+    "wolff_stats_read": (_I, [_P, _P, _I, _I]),
     "wolff_server_create": (_I, [_U64, _I, ctypes.POINTER(_P)]),
     "wolff_server_destroy": (_I, [_P]),
     "wolff_server_submit": (_I, [_P, ctypes.POINTER(JobDesc), ctypes.POINTER(_U64)]),
     "wolff_server_step": (_I, [_P, _D, ctypes.POINTER(_U64)]),
+    "wolff_server_set_lds": (_I, [_P, _I]),
     "wolff_server_status": (_I, [_P, _U64, ctypes.POINTER(_I), ctypes.POINTER(_U64)]),
     "wolff_server_finished": (_I, [_P, _P, _U64, ctypes.POINTER(_U64)]),
     "wolff_server_take": (_I, [_P, _U64, _P, _U64, ctypes.POINTER(_U64)]),
@@ -258,11 +273,20 @@ class Simulation:
     def set_lds_slab(self, slab_bits: int):
         _check(load().wolff_set_lds_slab(self._h, int(slab_bits)), "wolff_set_lds_slab")
 
+    def set_lds_tiles(self, wg: int):
+        _check(load().wolff_set_lds_tiles(self._h, int(wg)), "wolff_set_lds_tiles")
+
     def set_graph(self, chunk: int):
         _check(load().wolff_set_graph(self._h, int(chunk)), "wolff_set_graph")
 
     def set_tiles(self, wg: int, queue_entries: int):
         _check(load().wolff_set_tiles(self._h, int(wg), int(queue_entries)), "wolff_set_tiles")
+
+    def stats(self, reset: bool = False) -> dict:
+        """Counters of the counting build (libwolff_stats.so)."""
+        out = (ctypes.c_uint64 * STAT_COUNT)()
+        _check(load().wolff_stats_read(self._h, out, STAT_COUNT, 1 if reset else 0), "wolff_stats_read")
+        return {k: int(out[i]) for i, k in enumerate(STAT_NAMES)}
 
     def profile(self, on: bool):
         _check(load().wolff_profile(self._h, 1 if on else 0), "wolff_profile")
@@ -359,6 +383,16 @@ class Batch:
     def set_tiles(self, wg: int, queue_entries: int):
         _check(load().wolff_batch_set_tiles(self._h, wg, queue_entries), "wolff_batch_set_tiles")
 
+    def set_lds(self, on: bool):
+        _check(load().wolff_batch_set_lds(self._h, 1 if on else 0), "wolff_batch_set_lds")
+
+    def stats(self, reset: bool = False) -> dict:
+        """Counters of the counting build, summed over the replicas."""
+        out = (ctypes.c_uint64 * STAT_COUNT)()
+        _check(load().wolff_batch_stats_read(self._h, out, STAT_COUNT, 1 if reset else 0),
+               "wolff_batch_stats_read")
+        return {k: int(out[i]) for i, k in enumerate(STAT_NAMES)}
+
     def last_ms(self) -> float:
         ms = _D()
         _check(load().wolff_batch_last_ms(self._h, ctypes.byref(ms)), "wolff_batch_last_ms")
@@ -400,6 +434,9 @@ class Server:
                "wolff_server_submit")
         self.n_updates[jid.value] = int(job.n_updates)
         return jid.value
+
+    def set_lds(self, on: bool):
+        _check(load().wolff_server_set_lds(self._h, 1 if on else 0), "wolff_server_set_lds")
 
     def step(self, quantum_ms: float) -> int:
         n = _U64()

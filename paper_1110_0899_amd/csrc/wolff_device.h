@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/wolff.h"
+
 namespace wolff {
 
 // ------------------------------------------------------------------ Philox
@@ -320,5 +322,48 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
+
+// ------------------------------------------------------- counting build
+// Built with -DWOLFF_STATS=1 the kernels count what they do per lattice
+// (the WOLFF_STAT_* counters of the public header): sites expanded, steps,
+// neighbour reads, Philox blocks, claims, and the bytes of every global
+// memory access they issue (reads, writes, atomics).  Each thread keeps its
+// own counts; flush() sums them over each wave and adds them to the
+// lattice's counter array with one atomic per wave and counter.  In the
+// normal build the counts compile to nothing.
+#ifndef WOLFF_STATS
+#define WOLFF_STATS 0
+#endif
+
+struct StatAcc {
+#if WOLFF_STATS
+    unsigned long long c[WOLFF_STAT_COUNT] = {};
+#endif
+    __device__ __forceinline__ void add(int i, unsigned long long x)
+    {
+#if WOLFF_STATS
+        c[i] += x;
+#else
+        (void)i;
+        (void)x;
+#endif
+    }
+    __device__ __forceinline__ void flush(unsigned long long* dst)
+    {
+#if WOLFF_STATS
+        if (dst == nullptr) return;
+#pragma unroll
+        for (int i = 0; i < WOLFF_STAT_COUNT; ++i) {
+            unsigned long long v = c[i];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if ((threadIdx.x & 63u) == 0u && v != 0ull) atomicAdd(&dst[i], v);
+            c[i] = 0ull;
+        }
+#else
+        (void)dst;
+#endif
+    }
+};
 
 }  // namespace wolff

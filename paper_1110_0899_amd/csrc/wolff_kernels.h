@@ -42,6 +42,7 @@ struct Rep {
     int64_t M;              // magnetisation after the last update
     int64_t B;              // bond sum (valid when b_valid)
     const uint32_t* abort;  // host-mapped stop request, read once per update (NULL: none)
+    unsigned long long* stats;  // counting build: WOLFF_STAT_COUNT counters (NULL: none)
 };
 
 // Per-update control block of the team path.

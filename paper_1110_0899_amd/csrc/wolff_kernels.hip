@@ -52,7 +52,8 @@ template <int DIM, int SCOPE>
 __device__ __forceinline__ void expand_site(bool active, uint32_t j, const Geo& g, int8_t* S,
                                             int s0, uint32_t thr, uint32_t k0, uint32_t k1,
                                             uint32_t t, uint32_t s, uint32_t nb[2 * DIM],
-                                            bool won[2 * DIM], uint32_t pq = 0u, uint32_t c = 0u)
+                                            bool won[2 * DIM], uint32_t& n_act, uint32_t pq = 0u,
+                                            uint32_t c = 0u)
 {
     if (!active) j = 0u;
     uint32_t sa[2 * DIM];
@@ -66,6 +67,7 @@ __device__ __forceinline__ void expand_site(bool active, uint32_t j, const Geo& 
     for (int m = 0; m < 2 * DIM; ++m) {
         const uint32_t r = (m & 1) ? rm[m / 2] : rp[m / 2];
         const bool act = active && b[m] == s0 && r < thr;
+        n_act += act ? 1u : 0u;
         won[m] = act && (pq ? claim_colour<SCOPE>(S, sa[m], (uint32_t)s0, c) : claim<SCOPE>(S, sa[m], s0));
     }
 }
@@ -136,7 +138,7 @@ __device__ __forceinline__ void expand_site_wg(bool active, uint32_t j, const ui
                                                uint32_t k1, uint32_t t, uint32_t s,
                                                bool won[2 * DIM], uint32_t* tab,
                                                uint32_t& n_anti, uint32_t& n_inner,
-                                               uint32_t no_inner = 0u)
+                                               uint32_t& n_act, uint32_t no_inner = 0u)
 {
     uint32_t b[2 * DIM];
 #pragma unroll
@@ -149,6 +151,7 @@ __device__ __forceinline__ void expand_site_wg(bool active, uint32_t j, const ui
         const bool same = (b[m] & emask) == evalue;
         const uint32_t r = (m & 1) ? rm[m / 2] : rp[m / 2];
         act[m] = active && same && r < thr;
+        n_act += act[m] ? 1u : 0u;
         n_anti += (active && !same && !is_member(b[m], key)) ? 1u : 0u;
         n_inner += (active && is_expanded(b[m], key) && !((no_inner >> m) & 1u)) ? 1u : 0u;
     }
@@ -552,10 +555,33 @@ __device__ __forceinline__ uint32_t budget_spent(const WgCtl* c, uint64_t budget
 
 // Stop request of a lattice: a flag in host memory mapped into the device's
 // address space, set by the host while kernels run, read at system scope.
+// The loads and stores below go through global-address-space pointers: a
+// generic pointer would make them flat instructions, which every later LDS
+// wait of the wave would also wait for.
+typedef __attribute__((address_space(1))) const uint32_t gcword;
+typedef __attribute__((address_space(1))) int64_t gi64;
+
+// Record of one update at dst (three 8-byte global stores).
+__device__ __forceinline__ void store_record(wolff_record* dst, int64_t bond_sum, int64_t mag,
+                                             int64_t csize)
+{
+    gi64* p = (gi64*)dst;
+    p[0] = bond_sum;
+    p[1] = mag;
+    p[2] = csize;
+}
+
+// The raw request word (0: none); the caller compares it only where it
+// needs the answer, so that the host-memory read can stay in flight.
+__device__ __forceinline__ uint32_t abort_word(const uint32_t* flag)
+{
+    return flag != nullptr ? __hip_atomic_load((gcword*)flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)
+                           : 0u;
+}
+
 __device__ __forceinline__ uint32_t abort_requested(const uint32_t* flag)
 {
-    return (flag != nullptr &&
-            __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) ? 1u : 0u;
+    return abort_word(flag) != 0u ? 1u : 0u;
 }
 
 // Up to max_updates (0: all left) updates of replica R, stopping early at an
@@ -597,6 +623,12 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
     uint32_t err = 0u;
     const uint32_t QC = qmask + 1u;
     uint32_t* tab = q + QC;                                       // claim table after the ring
+    StatAcc st;                                                   // counting build only
+    // bytes one recount of the lattice reads (chunks of 16 sites with their
+    // +x word and +y (+z) chunks, or per site with its +mu neighbours)
+    const uint64_t recount_bytes = (g.tiled || (g.L & 15u) == 0u)
+                                       ? (uint64_t)(g.N / 16u) * (DIM == 2 ? 36u : 52u)
+                                       : (uint64_t)g.N * (1u + DIM);
 
     // a stop request seen before the first update: run none (the state
     // stays exact; the request is polled again after every update)
@@ -622,11 +654,17 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
             B = Bm;
             b_valid = true;
             clear_tags_wg<WG>(S, g.N);
+            // the normalisation pass reads every byte and rewrites the words with tags (bounded by N)
+            if (tid == 0) st.add(WOLFF_STAT_READ_BYTES, recount_bytes + g.N);
+            if (tid == 0) st.add(WOLFF_STAT_WRITE_BYTES, g.N);
             t_norm = t;
         }
         const uint32_t key = incr ? tag_key(t) : NO_TAG;
         const uint32_t s = seed_site(k0, k1, t, g.N);             // step (i)
         if (tid == 0) {
+            st.add(WOLFF_STAT_UPDATES, 1u);
+            st.add(WOLFF_STAT_READ_BYTES, 1u);
+            st.add(WOLFF_STAT_WRITE_BYTES, 1u);
             const uint32_t a = site_addr<DIM>(g, s);
             const uint32_t b0 = (uint8_t)SG[a];
             int s0;
@@ -658,7 +696,10 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
             uint32_t avail = tail - head;
             if (avail < (uint32_t)WG && ovn > 0u) {                 // refill the ring
                 const uint32_t m = min(ovn, QC - avail);
-                for (uint32_t i = tid; i < m; i += WG) q[(tail + i) & qmask] = ov[ovn - m + i];
+                for (uint32_t i = tid; i < m; i += WG) {
+                    q[(tail + i) & qmask] = ov[ovn - m + i];
+                    st.add(WOLFF_STAT_READ_BYTES, 4u);
+                }
                 tail += m;
                 ovn -= m;
                 __syncthreads();
@@ -685,8 +726,21 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
             uint32_t wm = 0u;                                         // odd L: slots that wrap around
             if (incr && odd && active) wm = wrap_slots<DIM>(g, j);
             bool won[2 * DIM];
+            uint32_t n_act = 0u;
             expand_site_wg<DIM, WG>(active, j, nb, sa, SG, emask, evalue, cb, key, thr, k0, k1, t,
-                                    s, won, tab, n_anti, n_inner, wm);
+                                    s, won, tab, n_anti, n_inner, n_act, wm);
+            if (tid == 0) st.add(WOLFF_STAT_STEPS, 1u);
+            if (active) {
+                uint32_t nw = 0u;
+#pragma unroll
+                for (int m = 0; m < 2 * DIM; ++m) nw += won[m] ? 1u : 0u;
+                st.add(WOLFF_STAT_SITES, 1u);
+                st.add(WOLFF_STAT_NEIGHBOUR_READS, 2u * DIM);
+                st.add(WOLFF_STAT_READ_BYTES, 2u * DIM);                // one byte per neighbour
+                st.add(WOLFF_STAT_PHILOX, 1u + DIM);                    // drawn during the gathers
+                st.add(WOLFF_STAT_CLAIMS, n_act);
+                st.add(WOLFF_STAT_WRITE_BYTES, nw + (incr ? 1u : 0u));  // flips, and the expanded tag
+            }
             if (incr && odd) {
                 // list the members on a last face (a +mu bond of theirs wraps
                 // around) below the top of the overflow stack: the stack holds
@@ -697,7 +751,10 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
                     uint32_t base = 0u;
                     if (lane == 0) base = atomicAdd(&ctl->faces, (uint32_t)__popcll(fm));
                     base = __shfl(base, 0, WAVE);
-                    if (face) ov[g.N - 1u - (base + lane_prefix(fm))] = j;
+                    if (face) {
+                        ov[g.N - 1u - (base + lane_prefix(fm))] = j;
+                        st.add(WOLFF_STAT_WRITE_BYTES, 4u);
+                    }
                 }
             }
             uint32_t pos[2 * DIM];
@@ -727,7 +784,10 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
             } else {
 #pragma unroll
                 for (int m = 0; m < 2 * DIM; ++m)
-                    if (won[m]) ov[ovn + before + pos[m]] = nb[m];
+                    if (won[m]) {
+                        ov[ovn + before + pos[m]] = nb[m];
+                        st.add(WOLFF_STAT_WRITE_BYTES, 4u);
+                    }
                 ovn += total;
             }
             csize += total;
@@ -746,6 +806,7 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
                 for (uint32_t i = tid; i < nf; i += WG) {
                     const uint32_t jf = ov[g.N - 1u - i];
                     const uint32_t wf = wrap_slots<DIM>(g, jf);
+                    st.add(WOLFF_STAT_READ_BYTES, 4u + (uint32_t)__popc(wf & 0x15u));
                     const uint32_t L = g.L;
                     uint32_t kk[DIM];
                     kk[0] = jf - (L - 1u);                            // +x of x = L - 1
@@ -772,20 +833,20 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
             reduce_lattice_wg<WG, DIM>(S, g, red, Bm, Mm, pq);
             B = Bm;
             if (Mm != M) err |= ERR_MAG;
+            if (tid == 0) st.add(WOLFF_STAT_READ_BYTES, recount_bytes);
         }
         b_valid = measure;
         if (tid == 0) {
-            wolff_record r;
-            r.bond_sum = measure ? B : (int64_t)WOLFF_NOT_MEASURED;
-            r.mag = M;
-            r.csize = (int64_t)csize;
-            rec[u] = r;
+            store_record(rec + u, measure ? B : (int64_t)WOLFF_NOT_MEASURED, M, (int64_t)csize);
+            st.add(WOLFF_STAT_WRITE_BYTES, 24u);
+            st.add(WOLFF_STAT_READ_BYTES, abort_flag != nullptr ? 4u : 0u);
             ctl->stop = budget_spent(ctl, budget) | abort_requested(abort_flag);
         }
         __syncthreads();
         ++done;
         if (ctl->stop) break;                 // at an update boundary only
     }
+    st.flush(R->stats);
     if (tid == 0) {
         R->t = t0 + done;
         R->n_left -= done;
@@ -934,6 +995,11 @@ __global__ void team_seed_kernel(Rep* R, TeamCtl* ctl, unsigned long long* gq)
     ctl->acc_neg = 0;
     ctl->blocks_done = 0u;
     gq[0] = ((unsigned long long)epoch << 32) | s;
+    if (WOLFF_STATS && R->stats) {
+        atomicAdd(&R->stats[WOLFF_STAT_UPDATES], 1ull);
+        atomicAdd(&R->stats[WOLFF_STAT_READ_BYTES], 1ull);
+        atomicAdd(&R->stats[WOLFF_STAT_WRITE_BYTES], 8ull + 1ull);      // queue entry 0 and the flip
+    }
 }
 
 template <int WG, int DIM>
@@ -961,6 +1027,7 @@ __global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned
 
     uint32_t head = 0u, tail = 0u;           // local ring
     uint64_t my_claims = 0u;
+    StatAcc st;                              // counting build only
     while (true) {
         if (tail == head) {
             // take a chunk from the global queue, or leave when pending is 0
@@ -968,6 +1035,7 @@ __global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned
                 uint32_t first = 0u, cnt = 0u, done = 0u;
                 uint32_t backoff = 1u, polls = 0u;
                 while (true) {
+                    st.add(WOLFF_STAT_READ_BYTES, 8u);          // head and tail
                     if (++polls > TEAM_SPIN_LIMIT) {           // never expected: flag and leave
                         __hip_atomic_fetch_or(&R->err, ERR_TEAM_WAIT, __ATOMIC_RELAXED, SCOPE_AGENT);
                         done = 1u;
@@ -979,6 +1047,7 @@ __global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned
                         uint32_t want = tl - h;
                         if (want > (uint32_t)WG) want = WG;
                         uint32_t expected = h;
+                        st.add(WOLFF_STAT_ATOMIC_BYTES, 4u);
                         if (__hip_atomic_compare_exchange_strong(&ctl->head, &expected, h + want,
                                                                  __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                                  SCOPE_AGENT)) {
@@ -988,6 +1057,8 @@ __global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned
                         }
                         continue;
                     }
+                    st.add(WOLFF_STAT_READ_BYTES, 4u);
+                    st.add(WOLFF_STAT_IDLE_POLLS, 1u);
                     if (__hip_atomic_load(&ctl->pending, __ATOMIC_RELAXED, SCOPE_AGENT) == 0) {
                         done = 1u;
                         break;
@@ -1009,6 +1080,7 @@ __global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned
                 // right after its reservation; the wait is bounded anyway
                 unsigned long long v = __hip_atomic_load(&gq[first + tid], __ATOMIC_RELAXED, SCOPE_AGENT);
                 uint32_t polls = 0u;
+                st.add(WOLFF_STAT_READ_BYTES, 8u);
                 while ((uint32_t)(v >> 32) != epoch) {
                     if (++polls > TEAM_SPIN_LIMIT) {
                         __hip_atomic_fetch_or(&R->err, ERR_TEAM_WAIT, __ATOMIC_RELAXED, SCOPE_AGENT);
@@ -1017,6 +1089,7 @@ __global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned
                     }
                     __builtin_amdgcn_s_sleep(1);
                     v = __hip_atomic_load(&gq[first + tid], __ATOMIC_RELAXED, SCOPE_AGENT);
+                    st.add(WOLFF_STAT_READ_BYTES, 8u);
                 }
                 q[(tail + tid) & qmask] = (uint32_t)v;
             }
@@ -1032,7 +1105,17 @@ __global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned
 
         uint32_t nb[2 * DIM];
         bool won[2 * DIM];
-        expand_site<DIM, SCOPE_AGENT>(active, j, g, S, s0, thr, k0, k1, t, s, nb, won, pq, cnew);
+        uint32_t n_act = 0u;
+        expand_site<DIM, SCOPE_AGENT>(active, j, g, S, s0, thr, k0, k1, t, s, nb, won, n_act, pq, cnew);
+        if (tid == 0) st.add(WOLFF_STAT_STEPS, 1u);
+        if (active) {
+            st.add(WOLFF_STAT_SITES, 1u);
+            st.add(WOLFF_STAT_NEIGHBOUR_READS, 2u * DIM);
+            st.add(WOLFF_STAT_READ_BYTES, 2u * DIM);
+            st.add(WOLFF_STAT_PHILOX, 1u + DIM);
+            st.add(WOLFF_STAT_CLAIMS, n_act);
+            st.add(WOLFF_STAT_ATOMIC_BYTES, 4u * n_act);      // 32-bit claim atomics
+        }
         uint32_t pos[2 * DIM];
         const uint32_t wtot = wave_compact<DIM>(won, pos);
         if (lane == 0) wave_cnt[wv] = wtot;
@@ -1054,6 +1137,7 @@ __global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned
             if (delta != 0) __hip_atomic_fetch_add(&ctl->pending, delta, __ATOMIC_RELAXED, SCOPE_AGENT);
             if (n_push > 0u)
                 sh_push = __hip_atomic_fetch_add(&ctl->tail, n_push, __ATOMIC_RELAXED, SCOPE_AGENT);
+            st.add(WOLFF_STAT_ATOMIC_BYTES, (delta != 0 ? 4u : 0u) + (n_push > 0u ? 4u : 0u));
         }
         __syncthreads();
         const uint32_t gbase = sh_push;
@@ -1066,6 +1150,7 @@ __global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned
                 } else {
                     const unsigned long long v = ((unsigned long long)epoch << 32) | nb[m];
                     __hip_atomic_store(&gq[gbase + (r - n_keep)], v, __ATOMIC_RELAXED, SCOPE_AGENT);
+                    st.add(WOLFF_STAT_WRITE_BYTES, 8u);
                 }
             }
         }
@@ -1074,6 +1159,8 @@ __global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned
         __syncthreads();
     }
 
+    if (tid == 0) st.add(WOLFF_STAT_ATOMIC_BYTES, (my_claims ? 8u : 0u) + 4u);
+    st.flush(R->stats);
     if (tid == 0) {
         if (my_claims)
             __hip_atomic_fetch_add(&ctl->csize, (unsigned long long)my_claims, __ATOMIC_RELAXED,
@@ -1122,6 +1209,15 @@ __global__ __launch_bounds__(256) void measure_grid_kernel(Rep* R, TeamCtl* ctl)
         red[NW + threadIdx.x / WAVE] = (long long)neg;
     }
     __syncthreads();
+    if (WOLFF_STATS && R->stats && blockIdx.x == 0 && threadIdx.x == 0) {
+        // the whole recount: 16-site chunks with their +x word and +y (+z) chunks
+        const uint64_t bytes = (g.tiled || (g.L & 15u) == 0u)
+                                   ? (uint64_t)(g.N / 16u) * (DIM == 2 ? 36u : 52u)
+                                   : (uint64_t)g.N * (1u + DIM);
+        atomicAdd(&R->stats[WOLFF_STAT_READ_BYTES], (unsigned long long)bytes);
+        atomicAdd(&R->stats[WOLFF_STAT_WRITE_BYTES], 24ull);
+        atomicAdd(&R->stats[WOLFF_STAT_ATOMIC_BYTES], 16ull * gridDim.x + 4ull * gridDim.x);
+    }
     if (threadIdx.x == 0) {
         long long sd = 0, sn = 0;
         for (int w = 0; w < NW; ++w) {

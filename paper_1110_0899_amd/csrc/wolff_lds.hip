@@ -169,7 +169,7 @@ __device__ __forceinline__ bool claim_bit(uint32_t* bits, uint32_t a, uint32_t b
 template <int WG, int DIM>
 __device__ __forceinline__ void slab_counts(const uint32_t* bits, const LdsGeo& lg, uint32_t g,
                                             const uint32_t* next_first_global, uint64_t& ndiff,
-                                            uint64_t& nneg)
+                                            uint64_t& nneg, StatAcc& st)
 {
     const uint32_t r0 = g * lg.slab_rows;
     const uint32_t nrows = min(lg.slab_rows, lg.rows - r0);
@@ -198,8 +198,10 @@ __device__ __forceinline__ void slab_counts(const uint32_t* bits, const LdsGeo& 
         const uint32_t r = r0 + lr;
         if (DIM == 2) {
             const uint32_t ry = (r + 1u == lg.rows) ? 0u : r + 1u;  // row of the +y neighbours
-            const uint32_t vy = (ry >= r0 && ry < r0 + nrows) ? bits[(ry - r0) * RW + wi]
-                                                              : ld_agent(&next_first_global[wi]);   // the next slab's first row
+            const bool here = ry >= r0 && ry < r0 + nrows;
+            const uint32_t vy = here ? bits[(ry - r0) * RW + wi]
+                                     : ld_agent(&next_first_global[wi]);   // the next slab's first row
+            st.add(WOLFF_STAT_READ_BYTES, here ? 0u : 4u);
             d += __popc((v ^ vy) & valid);
         } else {
             const uint32_t z = lg.dL.div(r);
@@ -207,8 +209,10 @@ __device__ __forceinline__ void slab_counts(const uint32_t* bits, const LdsGeo& 
             const uint32_t ry = (y + 1u == L) ? r + 1u - L : r + 1u;   // +y: within the plane
             d += __popc((v ^ bits[(ry - r0) * RW + wi]) & valid);
             const uint32_t rz = (r + L >= lg.rows) ? r + L - lg.rows : r + L;
-            const uint32_t vz = (rz >= r0 && rz < r0 + nrows) ? bits[(rz - r0) * RW + wi]
-                                                              : ld_agent(&next_first_global[y * RW + wi]);  // row y of the next slab's first plane
+            const bool here = rz >= r0 && rz < r0 + nrows;
+            const uint32_t vz = here ? bits[(rz - r0) * RW + wi]
+                                     : ld_agent(&next_first_global[y * RW + wi]);  // row y of the next slab's first plane
+            st.add(WOLFF_STAT_READ_BYTES, here ? 0u : 4u);
             d += __popc((v ^ vz) & valid);
         }
     }
@@ -276,7 +280,7 @@ __device__ __forceinline__ void lds_publish(const LdsArgs& a, LdsCtl* ctl, uint3
                                             const uint32_t nb[NS], uint32_t nproc,
                                             unsigned long long epoch, uint32_t b0, uint32_t gprev,
                                             uint32_t gnext, uint32_t G, uint32_t QC, uint32_t& head,
-                                            uint32_t& tail, uint32_t& ovn, uint32_t& claims)
+                                            uint32_t& tail, uint32_t& ovn, uint32_t& claims, StatAcc& st)
 {
     constexpr int NW = WG / WAVE;
     const uint32_t tid = threadIdx.x;
@@ -327,8 +331,10 @@ __device__ __forceinline__ void lds_publish(const LdsArgs& a, LdsCtl* ctl, uint3
                                                          __ATOMIC_RELAXED, SCOPE_AGENT);
                 sh[5] = ptot ? __hip_atomic_fetch_add(&a.inbox_tail[gprev], ptot, __ATOMIC_RELAXED, SCOPE_AGENT) : 0u;
                 sh[6] = ntot ? __hip_atomic_fetch_add(&a.inbox_tail[gnext], ntot, __ATOMIC_RELAXED, SCOPE_AGENT) : 0u;
+                st.add(WOLFF_STAT_ATOMIC_BYTES, 8u + (ptot ? 4u : 0u) + (ntot ? 4u : 0u));
             } else if (delta != 0) {
                 __hip_atomic_fetch_add(&ctl->P, (unsigned long long)delta, __ATOMIC_RELAXED, SCOPE_AGENT);
+                st.add(WOLFF_STAT_ATOMIC_BYTES, 8u);
             }
         }
         if (ptot + ntot > 0u) {
@@ -342,6 +348,8 @@ __device__ __forceinline__ void lds_publish(const LdsArgs& a, LdsCtl* ctl, uint3
                     const uint32_t slot = to_next[m] ? basen + nbf + spos[m] : basep + pb + spos[m];
                     __hip_atomic_store(&a.inbox[(size_t)dst * (a.imask + 1u) + (slot & a.imask)],
                                        word | nb[m], __ATOMIC_RELAXED, SCOPE_AGENT);
+                    st.add(WOLFF_STAT_WRITE_BYTES, 8u);
+                    st.add(WOLFF_STAT_MESSAGES, 1u);
                 }
             }
         }
@@ -354,10 +362,12 @@ __device__ __forceinline__ void lds_publish(const LdsArgs& a, LdsCtl* ctl, uint3
 #pragma unroll
     for (int m = 0; m < NS; ++m) {
         if (won[m]) {
-            if (fits)
+            if (fits) {
                 q[(qbase + pos[m]) & a.qmask] = nb[m];
-            else
+            } else {
                 ov[obase + pos[m]] = nb[m];
+                st.add(WOLFF_STAT_WRITE_BYTES, 4u);
+            }
         }
     }
     tail += fits ? total : 0u;
@@ -365,20 +375,33 @@ __device__ __forceinline__ void lds_publish(const LdsArgs& a, LdsCtl* ctl, uint3
     claims += total;
 }
 
-// MULTI: the lattice spans several slabs (G > 1, messages and grid
-// barriers); otherwise one workgroup holds it all and every team-only branch
-// compiles away.
+// Workgroup-shared words of the LDS path beside the slab and the ring.
+template <int NW>
+struct LdsShm {
+    uint32_t wave_cnt[NW];
+    uint32_t wave_snd[2 * NW];
+    uint64_t red[2 * NW];
+    uint32_t sh[8];
+};
+
+// All updates of one lattice (up to max_updates, or until the wall-clock
+// budget since t_start is spent) by this workgroup and, with MULTI, the
+// other G - 1 workgroups of the launch.  MULTI: the lattice spans several
+// slabs (messages, P, grid barriers through a.ctl); otherwise this one
+// workgroup holds it all, every team-only branch compiles away and a.ctl
+// is not used.
 template <int WG, int DIM, bool MULTI>
-__global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates)
+__device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates, uint64_t budget,
+                                         uint64_t t_start, uint32_t* lds, LdsShm<WG / WAVE>& shm)
 {
     constexpr int NW = WG / WAVE;
     constexpr int D2 = 2 * DIM;
     constexpr uint32_t BOND_SITES = (uint32_t)(WG / D2);    // sites of a one-lane-per-bond step
-    extern __shared__ __align__(16) uint32_t lds[];
-    __shared__ uint32_t wave_cnt[NW];
-    __shared__ uint32_t wave_snd[2 * NW];
-    __shared__ uint64_t red[2 * NW];
-    __shared__ uint32_t sh[8];
+    uint32_t* wave_cnt = shm.wave_cnt;
+    uint32_t* wave_snd = shm.wave_snd;
+    uint64_t* red = shm.red;
+    uint32_t* sh = shm.sh;
+    StatAcc st;                       // counting build only
 
     const LdsGeo lg = a.lg;
     uint32_t* bits = lds;
@@ -387,7 +410,7 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (WAVE - 1);
     const uint32_t wv = tid / WAVE;
-    const uint32_t g = blockIdx.x;
+    const uint32_t g = MULTI ? blockIdx.x : 0u;
     const uint32_t G = MULTI ? lg.G : 1u;
     const uint32_t r0 = g * lg.slab_rows;
     const uint32_t nrows = min(lg.slab_rows, lg.rows - r0);
@@ -417,6 +440,7 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
             const uint32_t j = base + x0 + b;
             const uint32_t addr = (DIM == 2) ? site_addr<2>(geo, j) : site_addr<3>(geo, j);
             v |= (((uint32_t)(uint8_t)SG[addr] >> 1) & 1u) << b;
+            st.add(WOLFF_STAT_READ_BYTES, 1u);
         }
         bits[w] = v;
     }
@@ -427,15 +451,19 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
         sh[3] = ihead;
     }
     // a stop request seen before the first update: run none
-    grid_barrier(ctl, G, [&] {
-        __hip_atomic_store(&ctl->stop, abort_requested(R->abort), __ATOMIC_RELAXED, SCOPE_AGENT);
-        __hip_atomic_store(&ctl->P, (unsigned long long)t0 << 32, __ATOMIC_RELAXED, SCOPE_AGENT);
-        ctl->M = R->M;
-        ctl->B = R->B;
-        ctl->acc_diff = ctl->acc_neg = ctl->acc_claims = 0ull;
-        ctl->acc_dm = 0ull;
-    });
-    if (tid == 0) sh[5] = __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, SCOPE_AGENT);
+    if (MULTI) {
+        grid_barrier(ctl, G, [&] {
+            __hip_atomic_store(&ctl->stop, abort_requested(R->abort), __ATOMIC_RELAXED, SCOPE_AGENT);
+            __hip_atomic_store(&ctl->P, (unsigned long long)t0 << 32, __ATOMIC_RELAXED, SCOPE_AGENT);
+            ctl->M = R->M;
+            ctl->B = R->B;
+            ctl->acc_diff = ctl->acc_neg = ctl->acc_claims = 0ull;
+            ctl->acc_dm = 0ull;
+        });
+        if (tid == 0) sh[5] = __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, SCOPE_AGENT);
+    } else {
+        if (tid == 0) sh[5] = abort_requested(R->abort);
+    }
     __syncthreads();
     ihead = sh[0];
     if (sh[5]) n = 0u;
@@ -451,14 +479,15 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
         const uint32_t t = t0 + done;
         // G = 1: the stop request is read now and used after the update, so
         // that the read's latency hides behind the growth
-        uint32_t abort_now = 0u;
-        if (G == 1u && tid == 0) abort_now = abort_requested(abort_flag);
+        uint32_t abort_raw = 0u;
+        if (G == 1u && tid == 0) abort_raw = abort_word(abort_flag);
         const unsigned long long epoch = (unsigned long long)(t + 1u) << 32;
         const uint32_t s = seed_site(k0, k1, t, lg.N);                // step (i)
         const uint32_t srow = lg.dL.div(s);
         const uint32_t owner = lg.dslab.div(srow);
         uint32_t head = 0u, tail = 0u, ovn = 0u;
         uint32_t claims = 0u, nstep = 0u;
+        if (tid == 0 && g == 0u) st.add(WOLFF_STAT_UPDATES, 1u);
         if (g == owner) {
             if (tid == 0) {
                 const uint32_t a0 = slab_bit(lg, s - srow * L, srow, r0);
@@ -481,7 +510,10 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
             uint32_t avail = tail - head;
             if (avail < (uint32_t)WG && ovn > 0u) {                 // refill the ring
                 const uint32_t m = min(ovn, QC - avail);
-                for (uint32_t i = tid; i < m; i += WG) q[(tail + i) & a.qmask] = ov[ovn - m + i];
+                for (uint32_t i = tid; i < m; i += WG) {
+                    q[(tail + i) & a.qmask] = ov[ovn - m + i];
+                    st.add(WOLFF_STAT_READ_BYTES, 4u);
+                }
                 tail += m;
                 ovn -= m;
                 __syncthreads();
@@ -494,6 +526,7 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
             if (G > 1u) {
                 if (avail == 0u) {
                     if (tid == 0) {
+                        const uint64_t c_idle = WOLFF_STATS ? clock64() : 0u;
                         uint32_t it = ld_agent(&a.inbox_tail[g]);
                         uint32_t fin = 0u;
                         uint32_t polls = 0u, backoff = 1u;
@@ -517,6 +550,9 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
                         }
                         sh[3] = it;
                         sh[4] = fin;
+                        st.add(WOLFF_STAT_IDLE_POLLS, polls + 1u);
+                        st.add(WOLFF_STAT_READ_BYTES, 4u + 12u * (polls + 1u));
+                        if (WOLFF_STATS) st.add(WOLFF_STAT_CYCLES_IDLE, clock64() - c_idle);
                     }
                     __syncthreads();
                     const uint32_t fin = sh[4];
@@ -539,6 +575,7 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
                     const unsigned long long* slot = &inbox[(ihead + tid) & a.imask];
                     unsigned long long v = ld_agent(slot);
                     uint32_t polls = 0u;
+                    st.add(WOLFF_STAT_READ_BYTES, 8u);
                     while ((v >> 32) != (epoch >> 32)) {          // reserved, not yet written
                         if (++polls > LDS_SPIN_LIMIT) {
                             flag_wait_failure(ctl);
@@ -546,6 +583,7 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
                         }
                         __builtin_amdgcn_s_sleep(1);
                         v = ld_agent(slot);
+                        st.add(WOLFF_STAT_READ_BYTES, 8u);
                     }
                     if ((v >> 32) == (epoch >> 32)) {
                         const uint32_t w = (uint32_t)v;
@@ -554,6 +592,7 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
                         sh[1] = b0;                               // every message carries s0
                         const uint32_t kr = lg.dL.div(k);
                         won = claim_bit(bits, slab_bit(lg, k - kr * L, kr, r0), b0);
+                        st.add(WOLFF_STAT_CLAIMS, 1u);
                     }
                 }
                 const uint64_t mask = __ballot(won);
@@ -572,6 +611,7 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
                     tail += total;
                 } else {
                     if (won) ov[ovn + before + pos] = k;
+                    st.add(WOLFF_STAT_WRITE_BYTES, won ? 4u : 0u);
                     ovn += total;
                 }
                 claims += total;
@@ -579,8 +619,10 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
                 if (tid == 0) {
                     sh[2] = 1u;
                     const long long delta = (long long)total - (long long)m;
-                    if (delta != 0)
+                    if (delta != 0) {
                         __hip_atomic_fetch_add(&ctl->P, (unsigned long long)delta, __ATOMIC_RELAXED, SCOPE_AGENT);
+                        st.add(WOLFF_STAT_ATOMIC_BYTES, 8u);
+                    }
                 }
                 __syncthreads();
                 continue;
@@ -597,6 +639,9 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
             const bool look = G > 1u && (nstep++ & 3u) == 0u;
             uint32_t it_async = 0u;
             if (look && tid == 0) it_async = ld_agent(&a.inbox_tail[g]);   // used at the end of the step
+            const uint64_t c_step = (WOLFF_STATS && tid == 0) ? clock64() : 0u;
+            if (tid == 0) st.add(WOLFF_STAT_STEPS, 1u);
+            if (look && tid == 0) st.add(WOLFF_STAT_READ_BYTES, 4u);
             if (avail <= BOND_SITES) {
                 const uint32_t si = tid / (uint32_t)D2;
                 const uint32_t m = tid - si * (uint32_t)D2;
@@ -607,7 +652,7 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
                 uint32_t nr, nc;
                 lds_neighbour<DIM>(lg, j, m, nr, nc);
                 const uint32_t nbk = nc + nr * L;
-                const bool local = nr >= r0 && nr < r0 + nrows;
+                const bool local = !MULTI || (nr >= r0 && nr < r0 + nrows);
                 const uint32_t ba = local ? slab_bit(lg, nc, nr, r0) : 0u;
                 const bool elig = active && (!local || bit_of(bits, ba) == b0);
                 uint32_t rr = 0xFFFFFFFFu;
@@ -622,8 +667,13 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
                 const bool snd[1] = {act && !local};
                 const bool to_next[1] = {(m & 1u) == 0u};
                 const uint32_t nb1[1] = {nbk};
+                st.add(WOLFF_STAT_SITES, (active && m == 0u) ? 1u : 0u);
+                st.add(WOLFF_STAT_NEIGHBOUR_READS, (active && local) ? 1u : 0u);
+                st.add(WOLFF_STAT_PHILOX, elig ? 1u : 0u);
+                st.add(WOLFF_STAT_CLAIMS, (act && local) ? 1u : 0u);
+                if (tid == 0) st.add(WOLFF_STAT_STEPS_NARROW, 1u);
                 lds_publish<WG, 1>(a, ctl, q, wave_cnt, wave_snd, sh, ov, won, snd, to_next, nb1, nproc,
-                                   epoch, b0, gprev, gnext, G, QC, head, tail, ovn, claims);
+                                   epoch, b0, gprev, gnext, G, QC, head, tail, ovn, claims, st);
             } else {
                 const uint32_t nproc = min(avail, (uint32_t)WG);
                 const bool active = tid < nproc;
@@ -636,7 +686,7 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
                     uint32_t nr, nc;
                     lds_neighbour<DIM>(lg, j, (uint32_t)m, nr, nc);
                     nb[m] = nc + nr * L;
-                    local[m] = nr >= r0 && nr < r0 + nrows;
+                    local[m] = !MULTI || (nr >= r0 && nr < r0 + nrows);
                     ba[m] = local[m] ? slab_bit(lg, nc, nr, r0) : 0u;
                     // a local neighbour is a candidate only if its spin is s0; a
                     // remote one is decided by its owner
@@ -668,10 +718,26 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
                 }
                 // every claim's LDS atomic in flight at once
                 claim_bits<D2>(bits, ba, act, b0, won);
+                if (active) {
+                    uint32_t nl = 0u, nc = 0u;
+#pragma unroll
+                    for (int m = 0; m < D2; ++m) {
+                        nl += local[m] ? 1u : 0u;
+                        nc += act[m] ? 1u : 0u;
+                    }
+                    uint32_t nblk = (elig[0] || elig[2] || (DIM == 3 && elig[D2 - 2])) ? 1u : 0u;
+#pragma unroll
+                    for (int mu = 0; mu < DIM; ++mu) nblk += elig[2 * mu + 1] ? 1u : 0u;
+                    st.add(WOLFF_STAT_SITES, 1u);
+                    st.add(WOLFF_STAT_NEIGHBOUR_READS, nl);
+                    st.add(WOLFF_STAT_PHILOX, nblk);
+                    st.add(WOLFF_STAT_CLAIMS, nc);
+                }
                 lds_publish<WG, D2>(a, ctl, q, wave_cnt, wave_snd, sh, ov, won, snd, to_next, nb, nproc,
-                                    epoch, b0, gprev, gnext, G, QC, head, tail, ovn, claims);
+                                    epoch, b0, gprev, gnext, G, QC, head, tail, ovn, claims, st);
             }
             if (look && tid == 0) sh[3] = it_async;
+            if (WOLFF_STATS && tid == 0) st.add(WOLFF_STAT_CYCLES_GROW, clock64() - c_step);
             __syncthreads();
         }
 
@@ -682,11 +748,13 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
             if (G > 1u) {
                 // publish the first row / plane for the previous slab's count
                 const uint32_t nb_words = (DIM == 2 ? 1u : L) * lg.RW;
-                for (uint32_t w = tid; w < nb_words; w += WG)
+                for (uint32_t w = tid; w < nb_words; w += WG) {
                     __hip_atomic_store(&a.bnd[(size_t)g * a.bnd_words + w], bits[w], __ATOMIC_RELAXED, SCOPE_AGENT);
+                    st.add(WOLFF_STAT_WRITE_BYTES, 4u);
+                }
                 grid_barrier(ctl, G, [] {});
             }
-            slab_counts<WG, DIM>(bits, lg, g, a.bnd + (size_t)gnext * a.bnd_words, ndiff, nneg);
+            slab_counts<WG, DIM>(bits, lg, g, a.bnd + (size_t)gnext * a.bnd_words, ndiff, nneg, st);
         }
         uint64_t dsum = wave_sum_u64(ndiff), nsum = wave_sum_u64(nneg);
         if (lane == 0) {
@@ -708,12 +776,15 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
                     B1 = (int64_t)DIM * (int64_t)lg.N - 2 * (int64_t)sd;
                     if ((int64_t)lg.N - 2 * (int64_t)sn != M1) err1 |= ERR_MAG;
                 }
-                wolff_record rr;
-                rr.bond_sum = measure ? B1 : (int64_t)WOLFF_NOT_MEASURED;
-                rr.mag = M1;
-                rr.csize = (int64_t)claims;
-                R->rec[rec0 + done] = rr;
-                sh[5] = abort_now | (err1 != 0u ? 1u : 0u);
+                store_record(R->rec + rec0 + done, measure ? B1 : (int64_t)WOLFF_NOT_MEASURED, M1,
+                             (int64_t)claims);
+                st.add(WOLFF_STAT_WRITE_BYTES, 24u);
+                st.add(WOLFF_STAT_READ_BYTES, 4u);                          // the stop request
+                // the request word is first looked at here (the empty asm keeps
+                // the compiler from testing it, and so waiting for it, earlier)
+                asm volatile("" : "+v"(abort_raw));
+                const bool spent = budget != 0u && wall_clock64() - t_start >= budget;
+                sh[5] = (abort_raw != 0u || err1 != 0u || spent) ? 1u : 0u;
             }
         } else {
             if (tid == 0) {
@@ -725,12 +796,14 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
                 if (measure) {
                     __hip_atomic_fetch_add(&ctl->acc_diff, (unsigned long long)sd, __ATOMIC_RELAXED, SCOPE_AGENT);
                     __hip_atomic_fetch_add(&ctl->acc_neg, (unsigned long long)sn, __ATOMIC_RELAXED, SCOPE_AGENT);
+                    st.add(WOLFF_STAT_ATOMIC_BYTES, 16u);
                 }
                 if (claims) {
                     // a slab that claimed sites knows s0: M changes by -2 s0 per claim
                     const long long dm = (b0 ? 2ll : -2ll) * (long long)claims;
                     __hip_atomic_fetch_add(&ctl->acc_claims, (unsigned long long)claims, __ATOMIC_RELAXED, SCOPE_AGENT);
                     __hip_atomic_fetch_add(&ctl->acc_dm, (unsigned long long)dm, __ATOMIC_RELAXED, SCOPE_AGENT);
+                    st.add(WOLFF_STAT_ATOMIC_BYTES, 16u);
                 }
             }
             grid_barrier(ctl, G, [&] {
@@ -747,11 +820,9 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
                 }
                 ctl->M = M;
                 ctl->B = B;
-                wolff_record rr;
-                rr.bond_sum = measure ? B : (int64_t)WOLFF_NOT_MEASURED;
-                rr.mag = M;
-                rr.csize = (int64_t)csize;
-                R->rec[rec0 + done] = rr;
+                store_record(R->rec + rec0 + done, measure ? B : (int64_t)WOLFF_NOT_MEASURED, M,
+                             (int64_t)csize);
+                st.add(WOLFF_STAT_WRITE_BYTES, 24u);
                 __hip_atomic_store(&ctl->acc_diff, 0ull, __ATOMIC_RELAXED, SCOPE_AGENT);
                 __hip_atomic_store(&ctl->acc_neg, 0ull, __ATOMIC_RELAXED, SCOPE_AGENT);
                 __hip_atomic_store(&ctl->acc_claims, 0ull, __ATOMIC_RELAXED, SCOPE_AGENT);
@@ -782,24 +853,88 @@ __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates
             const uint32_t j = base + x0 + b;
             const uint32_t addr = (DIM == 2) ? site_addr<2>(geo, j) : site_addr<3>(geo, j);
             SW[addr] = ((v >> b) & 1u) ? (int8_t)-1 : (int8_t)1;
+            st.add(WOLFF_STAT_WRITE_BYTES, 1u);
         }
     }
-    if (G == 1u && tid == 0) {
-        ctl->M = M1;
-        ctl->B = B1;
-        ctl->err |= err1;
+    st.flush(R->stats);
+    if (MULTI) {
+        grid_barrier(ctl, G, [&] {
+            R->t = t0 + done;
+            R->n_left -= done;
+            R->rec_count = rec0 + done;
+            R->M = ctl->M;
+            R->B = ctl->B;
+            if (done > 0u) R->b_valid = measure ? 1u : 0u;
+            R->t_norm = t0 + done;
+            R->err |= __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, SCOPE_AGENT);
+            __hip_atomic_store(&ctl->err, 0u, __ATOMIC_RELAXED, SCOPE_AGENT);
+        });
+    } else {
+        __syncthreads();                 // every thread is done with the descriptor
+        if (tid == 0) {
+            R->t = t0 + done;
+            R->n_left -= done;
+            R->rec_count = rec0 + done;
+            R->M = M1;
+            R->B = B1;
+            if (done > 0u) R->b_valid = measure ? 1u : 0u;
+            R->t_norm = t0 + done;
+            R->err |= err1;
+        }
+        __syncthreads();
     }
-    grid_barrier(ctl, G, [&] {
-        R->t = t0 + done;
-        R->n_left -= done;
-        R->rec_count = rec0 + done;
-        R->M = ctl->M;
-        R->B = ctl->B;
-        if (done > 0u) R->b_valid = measure ? 1u : 0u;
-        R->t_norm = t0 + done;
-        R->err |= __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, SCOPE_AGENT);
-        __hip_atomic_store(&ctl->err, 0u, __ATOMIC_RELAXED, SCOPE_AGENT);
-    });
+}
+
+// One lattice, on G workgroups (MULTI) or one.
+template <int WG, int DIM, bool MULTI>
+__global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates)
+{
+    extern __shared__ __align__(16) uint32_t lds[];
+    __shared__ LdsShm<WG / WAVE> shm;
+    lds_body<WG, DIM, MULTI>(a, max_updates, 0u, 0u, lds, shm);
+}
+
+// Batched form of the LDS path for lattices that fit one workgroup: each
+// workgroup takes replica order[blockIdx.x], then order[gridDim.x +
+// atomicAdd(next)], and runs it with its lattice in LDS (geos[r]: its
+// geometry) until the list or the wall-clock budget is exhausted, as the
+// one-workgroup batched kernel does with the lattice in global memory.
+// DIMS: 2, 3, or 0 for a list that mixes both.
+template <int WG, int DIMS>
+__global__ __launch_bounds__(WG) void lds_batch_kernel(Rep* reps, const LdsGeo* geos,
+                                                       const uint32_t* order, uint32_t n_reps,
+                                                       uint32_t* next, uint32_t max_updates,
+                                                       uint32_t qmask, uint64_t budget)
+{
+    extern __shared__ __align__(16) uint32_t lds[];
+    __shared__ LdsShm<WG / WAVE> shm;
+    __shared__ uint64_t t_start_sh;
+    __shared__ uint32_t idx_sh;
+    if (threadIdx.x == 0) t_start_sh = wall_clock64();
+    __syncthreads();
+    const uint64_t t_start = t_start_sh;
+    uint32_t idx = blockIdx.x;
+    while (idx < n_reps) {
+        const uint32_t r = __builtin_amdgcn_readfirstlane(order[idx]);
+        LdsArgs a{};
+        a.R = reps + r;
+        a.ctl = nullptr;
+        a.ov = reps[r].ov;
+        a.ov_stride = 0u;
+        a.qmask = qmask;
+        a.lg = geos[r];
+        if (DIMS == 2 || (DIMS == 0 && reps[r].dim == 2))
+            lds_body<WG, 2, false>(a, max_updates, budget, t_start, lds, shm);
+        else
+            lds_body<WG, 3, false>(a, max_updates, budget, t_start, lds, shm);
+        if (threadIdx.x == 0) {
+            const bool spent = budget != 0u && wall_clock64() - t_start >= budget;
+            idx_sh = spent ? n_reps : gridDim.x + atomicAdd(next, 1u);
+        }
+        __syncthreads();
+        idx = __builtin_amdgcn_readfirstlane(idx_sh);
+        __syncthreads();
+    }
 }
 
 }  // namespace wolff

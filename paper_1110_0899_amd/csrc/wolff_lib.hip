@@ -338,11 +338,14 @@ struct wolff_sim {
     uint32_t* lov = nullptr;
     size_t lbytes_inbox = 0, lbytes_tail = 0;
     uint32_t lds_slab_bits = 1u << 20;    // most spins of one workgroup's slab
+    int lds_wg = 0;                       // LDS-path workgroup size (0: by lattice size)
 
     int graph_chunk = 16;                 // updates per captured graph (0 = no graphs)
     hipGraphExec_t graph = nullptr;       // team-path chunk of graph_chunk updates
     int graph_key[3] = {-1, -1, -1};      // (chunk, measure, team size) it was captured with
     hipStream_t graph_stream = nullptr;
+
+    unsigned long long* d_stats = nullptr;   // counting build: WOLFF_STAT_COUNT counters
 
     bool profiling = false;
     std::vector<EventPair> ev_grow, ev_meas, ev_free;
@@ -450,6 +453,7 @@ static LdsFn lds_fn(int wg, int dim, uint32_t G)
     case 64: WOLFF_PICK_LDS(64);
     case 128: WOLFF_PICK_LDS(128);
     case 512: WOLFF_PICK_LDS(512);
+    case 1024: WOLFF_PICK_LDS(1024);
     default: WOLFF_PICK_LDS(256);
     }
 #undef WOLFF_PICK_LDS
@@ -513,6 +517,7 @@ static void free_sim(wolff_sim* s)
     if (s->d_order) (void)hipFree(s->d_order);
     if (s->d_next) (void)hipFree(s->d_next);
     if (s->d_ctl) (void)hipFree(s->d_ctl);
+    if (s->d_stats) (void)hipFree(s->d_stats);
     free_lds(s);
     if (s->abort_host) (void)hipHostFree(s->abort_host);
     if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
@@ -683,6 +688,10 @@ static int create_sim(int dim, int L, int q, double J, double T, uint64_t seed,
     CREATE_TRY(hipMalloc(&s->d_ctl, sizeof(TeamCtl)));
     CREATE_TRY(hipMemsetAsync(s->d_ctl, 0, sizeof(TeamCtl), s->stream));
     CREATE_TRY(hipMemsetAsync(s->d_order, 0, sizeof(uint32_t), s->stream));
+    if (WOLFF_STATS) {
+        CREATE_TRY(hipMalloc(&s->d_stats, WOLFF_STAT_COUNT * sizeof(unsigned long long)));
+        CREATE_TRY(hipMemsetAsync(s->d_stats, 0, WOLFF_STAT_COUNT * sizeof(unsigned long long), s->stream));
+    }
 
     if (!(ext && (ext->flags & WOLFF_BUFFERS_KEEP_SPINS))) {
         hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((N + 255) / 256, 65536)),
@@ -708,6 +717,7 @@ static int create_sim(int dim, int L, int q, double J, double T, uint64_t seed,
     r.measure = 1;
     r.err = 0;
     r.abort = s->abort_dev;
+    r.stats = s->d_stats;
     s->t = t0;
     CREATE_TRY(copy_wait(s->stream, s->d_rep, &r, sizeof(Rep), hipMemcpyHostToDevice));
     if ((rc = measure_now(s)) != WOLFF_OK) {
@@ -836,6 +846,7 @@ static int run_lds(wolff_sim* s, uint64_t n)
     LdsPlan p;
     if (!lds_plan(s->dim, (uint32_t)s->L, s->lds_slab_bits, &p))
         return fail(WOLFF_EINVAL, "lattice too large for the LDS path");
+    if (s->lds_wg) p.wg = s->lds_wg;
     int rc = ensure_lds(s, p);
     if (rc) return rc;
     wolff::LdsArgs a{};
@@ -972,6 +983,18 @@ extern "C" int wolff_set_lds_slab(wolff_sim* s, uint32_t slab_bits)
     free_lds(s);                               // sizes follow the slab count
     s->lds_slab_bits = slab_bits;
     if (s->path == WOLFF_PATH_LDS && !lds_fits(s)) s->path = WOLFF_PATH_AUTO;
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_set_lds_tiles(wolff_sim* s, int wg)
+{
+    if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
+    if (wg != 0 && wg != 64 && wg != 128 && wg != 256 && wg != 512 && wg != 1024)
+        return fail(WOLFF_EINVAL, "wg must be 0, 64, 128, 256, 512 or 1024");
+    if (wg == s->lds_wg) return WOLFF_OK;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    free_lds(s);                               // the kernel's LDS attribute is set on first use
+    s->lds_wg = wg;
     return WOLFF_OK;
 }
 
@@ -1244,7 +1267,72 @@ extern "C" int wolff_profile_read(wolff_sim* s, double* grow_ms, uint64_t* grow_
     return WOLFF_OK;
 }
 
+// Counters of a counting build (all zero and WOLFF_EINVAL otherwise).
+static int read_stats(hipStream_t st, unsigned long long* d, uint64_t* out, int n, int reset)
+{
+    if (!WOLFF_STATS || d == nullptr)
+        return fail(WOLFF_EINVAL, "the library was built without WOLFF_STATS (libwolff_stats.so counts)");
+    if (!out || n < 0) return fail(WOLFF_EINVAL, "bad output buffer");
+    unsigned long long h[WOLFF_STAT_COUNT];
+    HIP_TRY(copy_wait(st, h, d, sizeof(h), hipMemcpyDeviceToHost));
+    for (int i = 0; i < n && i < WOLFF_STAT_COUNT; ++i) out[i] = h[i];
+    if (reset) {
+        HIP_TRY(hipMemsetAsync(d, 0, sizeof(h), st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_stats_read(wolff_sim* s, uint64_t* out, int n, int reset)
+{
+    if (!s) return fail(WOLFF_EINVAL, "sim is NULL");
+    return read_stats(s->stream, s->d_stats, out, n, reset);
+}
+
 // ==================================================================== batch
+// One LDS class of a batch: replicas (longest expected work first), the
+// kernel's workgroup size and dimension variant, and its LDS bytes.
+struct BatchLdsClass {
+    std::vector<uint32_t> order;
+    uint32_t* d_order = nullptr;
+    int wg = 256;
+    int dims = 0;
+    size_t lds_bytes = 0;
+};
+
+// LDS classes of the batched LDS path: slabs of at most 32 KiB (square
+// lattices up to L = 512, simple-cubic up to L = 64; several workgroups
+// per CU) and the rest of the one-workgroup lattices (up to 128 KiB, one
+// workgroup per CU).  -1: not on the LDS path (Potts, or more than 2^20
+// spins).
+static constexpr uint32_t BATCH_LDS_RING = 2048;
+static int batch_lds_class(const wolff_job& j, wolff::LdsGeo* geo)
+{
+    if (j.q != 0) return -1;
+    LdsPlan p;
+    if (!lds_plan(j.dim, (uint32_t)j.L, LDS_SLAB_BITS, &p) || p.lg.G != 1u) return -1;
+    *geo = p.lg;
+    return p.lg.slab_words <= 8192u ? 0 : 1;
+}
+
+static size_t batch_lds_bytes_for(const wolff::LdsGeo& g)
+{
+    return ((size_t)((g.slab_words + 3u) & ~3u) + BATCH_LDS_RING) * sizeof(uint32_t);
+}
+
+using LdsBatchFn = void (*)(Rep*, const wolff::LdsGeo*, const uint32_t*, uint32_t, uint32_t*, uint32_t,
+                            uint32_t, uint64_t);
+
+static LdsBatchFn lds_batch_fn(int wg, int dims)
+{
+#define WOLFF_PICK_LB(W)                                                                \
+    return dims == 2 ? wolff::lds_batch_kernel<W, 2>                                     \
+                     : dims == 3 ? wolff::lds_batch_kernel<W, 3> : wolff::lds_batch_kernel<W, 0>
+    if (wg == 512) { WOLFF_PICK_LB(512); }
+    WOLFF_PICK_LB(256);
+#undef WOLFF_PICK_LB
+}
+
 struct wolff_batch {
     std::vector<wolff_job> jobs;
     std::vector<Rep> reps;          // host copy (pointers, geometry, parameters)
@@ -1270,12 +1358,39 @@ struct wolff_batch {
     bool use_graph = true;
     // captured (counter reset + persistent launch), keyed by its launch arguments
     std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
+    // Ising replicas whose lattice fits one workgroup's LDS run on the LDS
+    // path (lds_batch_kernel) in two classes by LDS size; the others (and
+    // all of them when use_lds is off) on the one-workgroup kernel above.
+    // The classes run as concurrent launches forked from the batch stream.
+    bool use_lds = true;
+    wolff::LdsGeo* d_geos = nullptr;
+    std::vector<uint32_t> order_glob;            // replicas outside the LDS classes
+    uint32_t* d_order_glob = nullptr;
+    int dims_glob = 0;
+    BatchLdsClass lcls[2];
+    uint32_t* d_next_aux = nullptr;              // work counters: [0] global class, [1..2] LDS classes
+    hipStream_t aux[2] = {nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+    unsigned long long* d_stats = nullptr;      // counting build: summed over the replicas
 };
 
 static void free_batch(wolff_batch* b)
 {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (hipStream_t st : b->aux)
+        if (st) (void)hipStreamSynchronize(st);
+    if (b->d_geos) (void)hipFree(b->d_geos);
+    if (b->d_stats) (void)hipFree(b->d_stats);
+    if (b->d_order_glob) (void)hipFree(b->d_order_glob);
+    for (auto& c : b->lcls)
+        if (c.d_order) (void)hipFree(c.d_order);
+    if (b->d_next_aux) (void)hipFree(b->d_next_aux);
+    for (hipStream_t st : b->aux)
+        if (st) (void)hipStreamDestroy(st);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    for (hipEvent_t e : b->ev_join)
+        if (e) (void)hipEventDestroy(e);
     if (b->S) (void)hipFree(b->S);
     if (b->ov) (void)hipFree(b->ov);
     if (b->rec) (void)hipFree(b->rec);
@@ -1344,6 +1459,10 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
     BATCH_TRY(hipMalloc(&b->d_next, sizeof(uint32_t)));
     BATCH_TRY(hipEventCreate(&b->ev_a));
     BATCH_TRY(hipEventCreate(&b->ev_b));
+    if (WOLFF_STATS) {
+        BATCH_TRY(hipMalloc(&b->d_stats, WOLFF_STAT_COUNT * sizeof(unsigned long long)));
+        BATCH_TRY(hipMemsetAsync(b->d_stats, 0, WOLFF_STAT_COUNT * sizeof(unsigned long long), b->stream));
+    }
     b->reps.resize(n_jobs);
     for (int i = 0; i < n_jobs; ++i) {
         const wolff_job& j = jobs[i];
@@ -1362,6 +1481,7 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
         r.t = 0;
         r.n_left = (uint32_t)j.n_updates;
         r.measure = (j.flags & WOLFF_JOB_UPDATE_ONLY) ? 0u : 1u;
+        r.stats = b->d_stats;
         if (j.start == 0) {
             hipLaunchKernelGGL(wolff::init_kernel, dim3(std::min<uint64_t>((Ns[i] + 255) / 256, 65536)),
                                dim3(256), 0, b->stream, r.S, r.geo, j.dim, r.k0, r.k1, r.q);
@@ -1390,6 +1510,47 @@ extern "C" int wolff_batch_create(const wolff_job* jobs, int n_jobs, wolff_batch
     });
     BATCH_TRY(copy_wait(b->stream, b->d_order, b->order.data(), n_jobs * sizeof(uint32_t),
                         hipMemcpyHostToDevice));
+    {   // LDS classes, each in the longest-first order above
+        std::vector<wolff::LdsGeo> geos(n_jobs);
+        std::vector<int> cls(n_jobs);
+        for (int i = 0; i < n_jobs; ++i) {
+            geos[i] = wolff::LdsGeo{};
+            cls[i] = batch_lds_class(jobs[i], &geos[i]);
+        }
+        for (uint32_t r : b->order) {
+            if (cls[r] < 0)
+                b->order_glob.push_back(r);
+            else
+                b->lcls[cls[r]].order.push_back(r);
+        }
+        b->dims_glob = b->order_glob.empty() ? 0 : jobs[b->order_glob[0]].dim;
+        for (uint32_t r : b->order_glob)
+            if (jobs[r].dim != b->dims_glob) b->dims_glob = 0;
+        BATCH_TRY(hipMalloc(&b->d_geos, n_jobs * sizeof(wolff::LdsGeo)));
+        BATCH_TRY(copy_wait(b->stream, b->d_geos, geos.data(), n_jobs * sizeof(wolff::LdsGeo),
+                            hipMemcpyHostToDevice));
+        BATCH_TRY(hipMalloc(&b->d_next_aux, 3 * sizeof(uint32_t)));
+        if (!b->order_glob.empty()) {
+            BATCH_TRY(hipMalloc(&b->d_order_glob, b->order_glob.size() * sizeof(uint32_t)));
+            BATCH_TRY(copy_wait(b->stream, b->d_order_glob, b->order_glob.data(),
+                                b->order_glob.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        }
+        for (int c = 0; c < 2; ++c) {
+            BatchLdsClass& C = b->lcls[c];
+            if (C.order.empty()) continue;
+            C.wg = c == 0 ? 256 : 512;
+            C.dims = jobs[C.order[0]].dim;
+            for (uint32_t r : C.order) {
+                if (jobs[r].dim != C.dims) C.dims = 0;
+                C.lds_bytes = std::max(C.lds_bytes, batch_lds_bytes_for(geos[r]));
+            }
+            BATCH_TRY(hipMalloc(&C.d_order, C.order.size() * sizeof(uint32_t)));
+            BATCH_TRY(copy_wait(b->stream, C.d_order, C.order.data(), C.order.size() * sizeof(uint32_t),
+                                hipMemcpyHostToDevice));
+            BATCH_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(lds_batch_fn(C.wg, C.dims)),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)C.lds_bytes));
+        }
+    }
     BATCH_TRY(hipStreamSynchronize(b->stream));
 #undef BATCH_TRY
     *out = b;
@@ -1437,6 +1598,66 @@ extern "C" int wolff_batch_set_stream(wolff_batch* b, void* hip_stream)
     return WOLFF_OK;
 }
 
+// One LDS-class launch of the batched LDS path on stream st.
+static hipError_t launch_lds_class(wolff_batch* b, int c, hipStream_t st, uint32_t max_updates)
+{
+    const BatchLdsClass& C = b->lcls[c];
+    const LdsBatchFn fn = lds_batch_fn(C.wg, C.dims);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), C.wg,
+                                                     C.lds_bytes) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const uint32_t n = (uint32_t)C.order.size();
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(n, (uint64_t)per_cu * device_cus());
+    uint32_t* next = b->d_next_aux + 1 + c;
+    hipLaunchKernelGGL(wolff::reset_counter_kernel, dim3(1), dim3(64), 0, st, next);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(C.wg), C.lds_bytes, st, b->d_reps, b->d_geos, C.d_order, n,
+                       next, max_updates, BATCH_LDS_RING - 1u, (uint64_t)0);
+    return hipGetLastError();
+}
+
+// The LDS classes and the rest as concurrent launches: the first on the
+// batch stream, the others on auxiliary streams that fork from it and
+// join back into it.
+static int run_batch_split(wolff_batch* b, uint32_t max_updates)
+{
+    std::vector<int> parts;                       // -1: the global class; 0, 1: LDS classes
+    if (!b->order_glob.empty()) parts.push_back(-1);
+    for (int c = 0; c < 2; ++c)
+        if (!b->lcls[c].order.empty()) parts.push_back(c);
+    for (size_t k = 1; k < parts.size(); ++k) {
+        if (!b->aux[k - 1]) HIP_TRY(hipStreamCreateWithFlags(&b->aux[k - 1], hipStreamNonBlocking));
+        if (!b->ev_join[k - 1]) HIP_TRY(hipEventCreateWithFlags(&b->ev_join[k - 1], hipEventDisableTiming));
+    }
+    if (!b->ev_fork) HIP_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(b->ev_a, b->stream));
+    HIP_TRY(hipEventRecord(b->ev_fork, b->stream));
+    for (size_t k = 0; k < parts.size(); ++k) {
+        hipStream_t st = k == 0 ? b->stream : b->aux[k - 1];
+        if (k > 0) HIP_TRY(hipStreamWaitEvent(st, b->ev_fork, 0));
+        if (parts[k] < 0) {
+            const uint32_t n = (uint32_t)b->order_glob.size();
+            const uint64_t resident = (uint64_t)batch_occupancy(b->wg, b->dims_glob, b->qentries);
+            const uint32_t grid = (uint32_t)std::min<uint64_t>(n, resident);
+            HIP_TRY(launch_batch(b->wg, b->dims_glob, grid, (uint32_t)b->qentries, st, b->d_reps,
+                                 b->d_order_glob, n, b->d_next_aux, max_updates));
+        } else {
+            HIP_TRY(launch_lds_class(b, parts[k], st, max_updates));
+        }
+        if (k > 0) HIP_TRY(hipEventRecord(b->ev_join[k - 1], st));
+    }
+    for (size_t k = 1; k < parts.size(); ++k) HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_join[k - 1], 0));
+    HIP_TRY(hipEventRecord(b->ev_b, b->stream));
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_batch_set_lds(wolff_batch* b, int on)
+{
+    if (!b) return fail(WOLFF_EINVAL, "batch is NULL");
+    b->use_lds = on != 0;
+    return WOLFF_OK;
+}
+
 extern "C" int wolff_batch_run(wolff_batch* b, uint64_t max_updates)
 {
     if (!b) return fail(WOLFF_EINVAL, "batch is NULL");
@@ -1444,6 +1665,17 @@ extern "C" int wolff_batch_run(wolff_batch* b, uint64_t max_updates)
     uint32_t active = 0;
     for (size_t i = 0; i < b->jobs.size(); ++i) active += b->left[i] > 0;
     if (active == 0) return WOLFF_OK;
+    if (b->use_lds && (!b->lcls[0].order.empty() || !b->lcls[1].order.empty())) {
+        const int rc = run_batch_split(b, (uint32_t)max_updates);
+        if (rc) return rc;
+        b->timed = true;
+        for (size_t i = 0; i < b->jobs.size(); ++i) {
+            const uint64_t m = (max_updates == 0) ? b->left[i] : std::min<uint64_t>(b->left[i], max_updates);
+            b->left[i] -= m;
+            b->t[i] += m;
+        }
+        return WOLFF_OK;
+    }
     const uint64_t resident = (uint64_t)batch_occupancy(b->wg, b->dims, b->qentries);
     const uint32_t n = (uint32_t)b->jobs.size();
     const uint32_t grid = (uint32_t)std::min<uint64_t>(n, resident);
@@ -1494,6 +1726,14 @@ extern "C" int wolff_batch_last_ms(wolff_batch* b, double* ms)
     HIP_TRY(hipEventElapsedTime(&f, b->ev_a, b->ev_b));
     *ms = f;
     return WOLFF_OK;
+}
+
+extern "C" int wolff_batch_stats_read(wolff_batch* b, uint64_t* out, int n, int reset)
+{
+    if (!b) return fail(WOLFF_EINVAL, "batch is NULL");
+    for (hipStream_t st : b->aux)
+        if (st) HIP_TRY(hipStreamSynchronize(st));
+    return read_stats(b->stream, b->d_stats, out, n, reset);
 }
 
 extern "C" int wolff_batch_progress(wolff_batch* b, int job, uint64_t* left, uint64_t* t)
@@ -1577,6 +1817,19 @@ struct wolff_server {
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
     uint64_t quanta = 0, updates = 0, added = 0;
     double gpu_ms = 0.0;
+    // LDS classes of the batched form (as in wolff_batch): per quantum, the
+    // running Ising jobs that fit one workgroup's LDS go to lds_batch_kernel
+    // launches (up to each class's resident workgroups; the overflow and
+    // every other job to the one-workgroup kernel), all three concurrent
+    bool use_lds = true;
+    wolff::LdsGeo* h_geos = nullptr;    // pinned staging, one per slot
+    wolff::LdsGeo* d_geos = nullptr;
+    uint32_t* h_lists = nullptr;        // pinned: three slot lists of `slots` entries
+    uint32_t* d_lists = nullptr;
+    uint32_t* d_next3 = nullptr;
+    hipStream_t aux[2] = {nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+    int lds_cap[2] = {0, 0};            // resident workgroups of each LDS class
 };
 
 static void free_server(wolff_server* v)
@@ -1587,6 +1840,19 @@ static void free_server(wolff_server* v)
             if (kv.second.block) (void)hipFreeAsync(kv.second.block, v->stream);
         (void)hipStreamSynchronize(v->stream);
     }
+    for (hipStream_t st : v->aux)
+        if (st) {
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
+        }
+    if (v->ev_fork) (void)hipEventDestroy(v->ev_fork);
+    for (hipEvent_t e : v->ev_join)
+        if (e) (void)hipEventDestroy(e);
+    if (v->h_geos) (void)hipHostFree(v->h_geos);
+    if (v->d_geos) (void)hipFree(v->d_geos);
+    if (v->h_lists) (void)hipHostFree(v->h_lists);
+    if (v->d_lists) (void)hipFree(v->d_lists);
+    if (v->d_next3) (void)hipFree(v->d_next3);
     if (v->h_reps) (void)hipHostFree(v->h_reps);
     if (v->d_reps) (void)hipFree(v->d_reps);
     if (v->d_order) (void)hipFree(v->d_order);
@@ -1636,6 +1902,27 @@ extern "C" int wolff_server_create(uint64_t hbm_budget_bytes, int max_slots, wol
     }
     SRV_TRY(hipEventCreate(&v->ev_a));
     SRV_TRY(hipEventCreate(&v->ev_b));
+    SRV_TRY(hipHostMalloc((void**)&v->h_geos, v->slots * sizeof(wolff::LdsGeo), hipHostMallocDefault));
+    SRV_TRY(hipMalloc(&v->d_geos, v->slots * sizeof(wolff::LdsGeo)));
+    SRV_TRY(hipHostMalloc((void**)&v->h_lists, 3 * v->slots * sizeof(uint32_t), hipHostMallocDefault));
+    SRV_TRY(hipMalloc(&v->d_lists, 3 * v->slots * sizeof(uint32_t)));
+    SRV_TRY(hipMalloc(&v->d_next3, 3 * sizeof(uint32_t)));
+    for (int k = 0; k < 2; ++k) {
+        SRV_TRY(hipStreamCreateWithFlags(&v->aux[k], hipStreamNonBlocking));
+        SRV_TRY(hipEventCreateWithFlags(&v->ev_join[k], hipEventDisableTiming));
+    }
+    SRV_TRY(hipEventCreateWithFlags(&v->ev_fork, hipEventDisableTiming));
+    for (int c = 0; c < 2; ++c) {
+        // the mixed-dimension kernels, with the LDS of each class's largest lattice
+        const int wg = c == 0 ? 256 : 512;
+        const size_t bytes = ((size_t)(c == 0 ? 8192u : 32768u) + BATCH_LDS_RING) * sizeof(uint32_t);
+        const void* fn = reinterpret_cast<const void*>(lds_batch_fn(wg, 0));
+        SRV_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, wg, bytes) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        v->lds_cap[c] = per_cu * device_cus();
+    }
 #undef SRV_TRY
     *out = v;
     return WOLFF_OK;
@@ -1716,6 +2003,59 @@ static int server_admit(wolff_server* v)
     return WOLFF_OK;
 }
 
+// One quantum over the n running slots in up to three concurrent launches:
+// the LDS classes (slot lists 1 and 2, at most each class's resident
+// workgroups) and the one-workgroup kernel for the rest (list 0).  The slot
+// descriptors are already on the device.
+static int server_split_quantum(wolff_server* v, uint32_t n, uint64_t budget)
+{
+    uint32_t cnt[3] = {0u, 0u, 0u};
+    uint32_t* lists[3] = {v->h_lists, v->h_lists + v->slots, v->h_lists + 2 * v->slots};
+    for (uint32_t i = 0; i < n; ++i) {
+        const SrvJob& j = v->jobs.at(v->running[i]);
+        wolff::LdsGeo g{};
+        int c = batch_lds_class(j.spec, &g);
+        if (c >= 0 && cnt[1 + c] >= (uint32_t)v->lds_cap[c]) c = -1;   // class full: global kernel
+        v->h_geos[i] = g;
+        lists[1 + c][cnt[1 + c]++] = i;
+    }
+    HIP_TRY(hipMemcpyAsync(v->d_geos, v->h_geos, n * sizeof(wolff::LdsGeo), hipMemcpyHostToDevice, v->stream));
+    HIP_TRY(hipMemcpyAsync(v->d_lists, v->h_lists, 3 * v->slots * sizeof(uint32_t), hipMemcpyHostToDevice,
+                           v->stream));
+    HIP_TRY(hipEventRecord(v->ev_fork, v->stream));
+    int k = 0;                                                       // launches so far
+    for (int part = 0; part < 3; ++part) {
+        if (cnt[part] == 0) continue;
+        hipStream_t st = k == 0 ? v->stream : v->aux[k - 1];
+        if (k > 0) HIP_TRY(hipStreamWaitEvent(st, v->ev_fork, 0));
+        const uint32_t* d_list = v->d_lists + (size_t)part * v->slots;
+        uint32_t* next = v->d_next3 + part;
+        if (part == 0) {
+            HIP_TRY(launch_batch(v->wg, 0, cnt[0], (uint32_t)v->qentries, st, v->d_reps, d_list, cnt[0],
+                                 next, 0u, budget));
+        } else {
+            const int c = part - 1;
+            const int wg = c == 0 ? 256 : 512;
+            const size_t bytes = ((size_t)(c == 0 ? 8192u : 32768u) + BATCH_LDS_RING) * sizeof(uint32_t);
+            hipLaunchKernelGGL(wolff::reset_counter_kernel, dim3(1), dim3(64), 0, st, next);
+            hipLaunchKernelGGL(lds_batch_fn(wg, 0), dim3(cnt[part]), dim3(wg), bytes, st, v->d_reps,
+                               v->d_geos, d_list, cnt[part], next, 0u, BATCH_LDS_RING - 1u, budget);
+            HIP_TRY(hipGetLastError());
+        }
+        if (k > 0) HIP_TRY(hipEventRecord(v->ev_join[k - 1], st));
+        ++k;
+    }
+    for (int m = 1; m < k; ++m) HIP_TRY(hipStreamWaitEvent(v->stream, v->ev_join[m - 1], 0));
+    return WOLFF_OK;
+}
+
+extern "C" int wolff_server_set_lds(wolff_server* v, int on)
+{
+    if (!v) return fail(WOLFF_EINVAL, "server is NULL");
+    v->use_lds = on != 0;
+    return WOLFF_OK;
+}
+
 extern "C" int wolff_server_step(wolff_server* v, double quantum_ms, uint64_t* n_finished)
 {
     if (!v || !(quantum_ms >= 0.0)) return fail(WOLFF_EINVAL, "bad argument");
@@ -1737,8 +2077,12 @@ extern "C" int wolff_server_step(wolff_server* v, double quantum_ms, uint64_t* n
         }
         const uint64_t budget = (uint64_t)(quantum_ms * (double)v->ticks_per_ms);
         HIP_TRY(hipEventRecord(v->ev_a, v->stream));
-        HIP_TRY(launch_batch(v->wg, 0, n, (uint32_t)v->qentries, v->stream, v->d_reps, v->d_order, n,
-                             v->d_next, 0u, budget == 0 ? 1 : budget));
+        if (v->use_lds) {
+            if ((rc = server_split_quantum(v, n, budget == 0 ? 1 : budget))) return rc;
+        } else {
+            HIP_TRY(launch_batch(v->wg, 0, n, (uint32_t)v->qentries, v->stream, v->d_reps, v->d_order, n,
+                                 v->d_next, 0u, budget == 0 ? 1 : budget));
+        }
         HIP_TRY(hipEventRecord(v->ev_b, v->stream));
         HIP_TRY(hipMemcpyAsync(v->h_reps, v->d_reps, n * sizeof(Rep), hipMemcpyDeviceToHost, v->stream));
         HIP_TRY(hipStreamSynchronize(v->stream));

@@ -183,11 +183,18 @@ def test_special_cases():
     assert (got[:, 2] == 216).all() and (got[:, 0] == 3 * 216).all()
 
 
-def test_batch_matches_alone():
+@pytest.mark.parametrize("lds", [True, False])
+def test_batch_matches_alone(lds):
+    # lds: these lattices run on the batched LDS path, in both LDS-size
+    # classes (the square L = 600 and cubic L = 70 lattices need more than
+    # 32 KiB of LDS); off: all on the one-workgroup kernel
     jobs = [workloads.Job(2, 32, TC2, 11, 400), workloads.Job(3, 8, T3, 12, 300),
             workloads.Job(2, 17, 2.5, 13, 350), workloads.Job(2, 128, 2.0, 14, 60),
-            workloads.Job(3, 5, 4.0, 15, 500), workloads.Job(2, 2, 1.0, 16, 100)]
+            workloads.Job(3, 5, 4.0, 15, 500), workloads.Job(2, 2, 1.0, 16, 100),
+            workloads.Job(2, 600, TC2, 17, 30), workloads.Job(3, 70, T3, 18, 40)]
+    print("case batch lds=%d" % lds, flush=True)
     with binding.Batch(jobs) as b:
+        b.set_lds(lds)
         b.run(150)                      # one launch, at most 150 updates each
         b.run()                          # the rest
         for i, j in enumerate(jobs):
@@ -248,8 +255,10 @@ def test_team_graph_replays_match_oracle(measure):
 
 
 def test_batch_graph_replays_match_oracle():
+    # graphs serve the one-workgroup kernel's launches
     jobs = [workloads.Job(2, 24, TC2, 61, 90), workloads.Job(3, 6, T3, 62, 90)]
     with binding.Batch(jobs) as b:
+        b.set_lds(False)
         b.set_graph(True)
         for _ in range(6):                 # the same captured launch replayed 6 times
             b.run(15)
@@ -393,6 +402,7 @@ def test_tile_sizes_single_and_batch(wg, q):
             assert (sim.spins() == Sref).all()
     jobs = [workloads.Job(d, L, T, seed, n) for d, L, T, seed, n in cases]
     with binding.Batch(jobs) as b:
+        b.set_lds(False)                   # the tiles are the one-workgroup kernel's
         b.set_tiles(wg, q)
         b.run()
         for i, (d, L, T, seed, n) in enumerate(cases):

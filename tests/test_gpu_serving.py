@@ -61,9 +61,12 @@ def gpu():
     binding.load()
 
 
-def test_batch_budgeted_quanta_match_oracle():
+@pytest.mark.parametrize("lds", [True, False])
+def test_batch_budgeted_quanta_match_oracle(lds):
     jobs = mixed_jobs(24, seed=1)
+    print("case budgeted quanta lds=%d" % lds, flush=True)
     with binding.Batch(jobs) as b:
+        b.set_lds(lds)
         for _ in range(200):
             if all(b.progress(i)[0] == 0 for i in range(len(jobs))):
                 break
@@ -92,10 +95,15 @@ def test_mixed_c4_style_batch_against_oracle():
             assert (b.spins(i) == S).all(), i
 
 
-def test_server_mix_matches_oracle():
+@pytest.mark.parametrize("lds", [True, False])
+def test_server_mix_matches_oracle(lds):
+    # lds: the jobs that fit one workgroup's LDS run each quantum on the
+    # batched LDS path, concurrently with the rest on the one-workgroup kernel
     jobs = mixed_jobs(40, seed=2)
     results = {}
+    print("case server mix lds=%d" % lds, flush=True)
     with binding.Server() as srv:
+        srv.set_lds(lds)
         ids = {}
         # submit in waves between quanta: later jobs join while earlier ones run
         for wave in range(4):
