@@ -239,19 +239,30 @@ def c4_leg(binding, workloads, n_updates):
     # The makespan is set by the largest replicas once their clusters have
     # grown; an early window (clusters still small) favours small workgroups
     # (128 threads: 17.7 s against 10.4 s with 256 over the whole run).
-    tuned = autotune.tune(workloads.c4_jobs(2400), warm=2000, timed=400, start=0, log=log)
+    # tiles of the one-workgroup kernel, tuned for each setting (with the LDS
+    # classes it only runs the replicas that do not fit one workgroup's LDS)
+    tuned = {lds: autotune.tune(workloads.c4_jobs(2400), warm=2000, timed=400, start=0, log=log,
+                                lds=lds) for lds in (True, False)}
+
     def run(lds):
         b = binding.Batch(jobs, start=0)
-        b.set_tiles(tuned["wg"], tuned["queue_entries"])
+        b.set_tiles(tuned[lds]["wg"], tuned[lds]["queue_entries"])
         b.set_measure(True)
         b.set_lds(lds)
         a = time.perf_counter()
         b.run()
         ms = b.last_ms()
         wall = time.perf_counter() - a
-        added = sum(int(b.records(i)["csize"].sum()) for i in range(len(jobs)))
+        per = [int(b.records(i)["csize"].sum()) for i in range(len(jobs))]
         b.close()
-        return wall, ms, added
+        if lds:
+            # the replicas with the most work (sites flipped over the run)
+            top = sorted(range(len(jobs)), key=lambda i: -per[i])[:5]
+            heavy.extend({"dim": jobs[i].dim, "L": jobs[i].L, "T": round(jobs[i].T, 4),
+                          "added": per[i]} for i in top)
+        return wall, ms, sum(per)
+
+    heavy = []
 
     # the replicas that fit one workgroup's LDS run on the batched LDS path;
     # the same set all on the one-workgroup kernel, for comparison
@@ -266,7 +277,10 @@ def c4_leg(binding, workloads, n_updates):
             "kernel_s": ms * 1e-3, "added": added, "added_per_s": added / wall,
             "cluster_updates_per_s": len(jobs) * n_updates / wall,
             "replicas_on_lds_path": n_lds, "makespan_one_workgroup_kernel_s": wall_g,
-            "wg": tuned["wg"], "queue_entries": tuned["queue_entries"]}
+            "wg": tuned[True]["wg"], "queue_entries": tuned[True]["queue_entries"],
+            "heaviest_replicas": heavy,
+            "wg_one_workgroup_kernel": tuned[False]["wg"],
+            "queue_entries_one_workgroup_kernel": tuned[False]["queue_entries"]}
 
 
 PAPER_TABLES = {  # ms per update at T_c on the paper's GTX 285 / one Xeon W3520 core (Tables 1-2):

@@ -65,9 +65,12 @@ def _store(k: str, v: dict):
         pass
 
 
-def measure(jobs, wg: int, q: int, warm: int, timed: int, start: int) -> float:
-    """Kernel milliseconds of `timed` updates of every replica after `warm`."""
+def measure(jobs, wg: int, q: int, warm: int, timed: int, start: int, lds: bool = True) -> float:
+    """Kernel milliseconds of `timed` updates of every replica after `warm`
+    (lds: the replicas that fit one workgroup's LDS on the LDS path, whose
+    timing the tiles do not change)."""
     with binding.Batch(jobs, start=start) as b:
+        b.set_lds(lds)
         b.set_tiles(wg, q)
         if warm:
             b.run(warm)
@@ -92,9 +95,10 @@ def set_key(jobs) -> str:
 
 
 def tune(jobs, warm: int = 4, timed: int = 4, start: int = 1, candidates=None,
-         use_cache: bool = True, log=None) -> dict:
-    """Best (wg, queue_entries) for a list of jobs (cached per set_key)."""
-    k = set_key(jobs)
+         use_cache: bool = True, log=None, lds: bool = True) -> dict:
+    """Best (wg, queue_entries) of the one-workgroup kernel for a list of
+    jobs (cached per set_key and LDS setting)."""
+    k = set_key(jobs) + ("" if lds else "|no-lds")
     if use_cache:
         hit = _load_cache().get(k)
         if hit:
@@ -104,7 +108,7 @@ def tune(jobs, warm: int = 4, timed: int = 4, start: int = 1, candidates=None,
     trials = []
     t0 = time.time()
     for wg, q in cands:
-        ms = measure(jobs, wg, q, warm, timed, start)
+        ms = measure(jobs, wg, q, warm, timed, start, lds)
         trials.append({"wg": wg, "queue_entries": q, "ms": ms})
         if log:
             log("tune %s: wg=%d q=%d -> %.1f ms" % (k, wg, q, ms))

@@ -726,9 +726,14 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
             uint32_t wm = 0u;                                         // odd L: slots that wrap around
             if (incr && odd && active) wm = wrap_slots<DIM>(g, j);
             bool won[2 * DIM];
+#pragma unroll
+            for (int m = 0; m < 2 * DIM; ++m) won[m] = false;
             uint32_t n_act = 0u;
-            expand_site_wg<DIM, WG>(active, j, nb, sa, SG, emask, evalue, cb, key, thr, k0, k1, t,
-                                    s, won, tab, n_anti, n_inner, n_act, wm);
+            // a wave with no frontier site this step skips the gathers and the
+            // Philox blocks (its SIMD's issue slots go to the waves that work)
+            if (__ballot(active) != 0ull)
+                expand_site_wg<DIM, WG>(active, j, nb, sa, SG, emask, evalue, cb, key, thr, k0, k1, t,
+                                        s, won, tab, n_anti, n_inner, n_act, wm);
             if (tid == 0) st.add(WOLFF_STAT_STEPS, 1u);
             if (active) {
                 uint32_t nw = 0u;
@@ -865,8 +870,15 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
 // advanced by one workgroup per launch, so its claims need no device-scope
 // atomics (they are settled in LDS); the kernel boundary publishes its state
 // to the next launch.
+// Waves per SIMD the 512- and 1024-thread batched kernels are compiled for
+// (0: as many as their registers allow).
+#ifndef WOLFF_BATCH_WAVES
+#define WOLFF_BATCH_WAVES 0
+#endif
+
 template <int WG, int DIMS>
-__global__ __launch_bounds__(WG) void batch_kernel(Rep* reps, const uint32_t* order,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(
+    (WG >= 512 && WOLFF_BATCH_WAVES > 0) ? WOLFF_BATCH_WAVES : 1))) void batch_kernel(Rep* reps, const uint32_t* order,
                                                    uint32_t n_reps, uint32_t* next,
                                                    uint32_t max_updates, uint32_t qmask,
                                                    uint64_t budget)
@@ -1106,7 +1118,10 @@ __global__ __launch_bounds__(WG) void team_kernel(Rep* R, TeamCtl* ctl, unsigned
         uint32_t nb[2 * DIM];
         bool won[2 * DIM];
         uint32_t n_act = 0u;
-        expand_site<DIM, SCOPE_AGENT>(active, j, g, S, s0, thr, k0, k1, t, s, nb, won, n_act, pq, cnew);
+#pragma unroll
+        for (int m = 0; m < 2 * DIM; ++m) won[m] = false;
+        if (__ballot(active) != 0ull)           // idle waves skip the gathers and Philox blocks
+            expand_site<DIM, SCOPE_AGENT>(active, j, g, S, s0, thr, k0, k1, t, s, nb, won, n_act, pq, cnew);
         if (tid == 0) st.add(WOLFF_STAT_STEPS, 1u);
         if (active) {
             st.add(WOLFF_STAT_SITES, 1u);

@@ -303,23 +303,27 @@ __device__ __forceinline__ void lds_publish(const LdsArgs& a, LdsCtl* ctl, uint3
         sprev += (uint32_t)__popcll(mp);
         snext += (uint32_t)__popcll(mn);
     }
-    if (lane == 0) {
-        wave_cnt[wv] = wtot;
-        wave_snd[wv] = sprev;
-        wave_snd[NW + wv] = snext;
-    }
-    __syncthreads();
-    uint32_t before = 0u, total = 0u, pb = 0u, ptot = 0u, nbf = 0u, ntot = 0u;
+    uint32_t before = 0u, total = wtot, pb = 0u, ptot = sprev, nbf = 0u, ntot = snext;
+    if (NW > 1) {
+        // the waves' counts through LDS (one wave has its totals already)
+        if (lane == 0) {
+            wave_cnt[wv] = wtot;
+            wave_snd[wv] = sprev;
+            wave_snd[NW + wv] = snext;
+        }
+        __syncthreads();
+        total = ptot = ntot = 0u;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        const uint32_t c = wave_cnt[w], cp = wave_snd[w], cn = wave_snd[NW + w];
-        const bool lower = (uint32_t)w < wv;
-        before += lower ? c : 0u;
-        pb += lower ? cp : 0u;
-        nbf += lower ? cn : 0u;
-        total += c;
-        ptot += cp;
-        ntot += cn;
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t c = wave_cnt[w], cp = wave_snd[w], cn = wave_snd[NW + w];
+            const bool lower = (uint32_t)w < wv;
+            before += lower ? c : 0u;
+            pb += lower ? cp : 0u;
+            nbf += lower ? cn : 0u;
+            total += c;
+            ptot += cp;
+            ntot += cn;
+        }
     }
     if (G > 1u) {
         if (tid == 0) {

@@ -428,7 +428,12 @@ static bool lds_plan(int dim, uint32_t L, uint32_t slab_bits, LdsPlan* out)
     LdsPlan p{};
     p.lg = lg;
     const uint64_t N = lg.N;
-    p.wg = lg.G > 1u ? 256 : N <= 4096 ? 64 : N <= 16384 ? 128 : N < (1u << 18) ? 256 : 512;
+    // measured on MI355X at the critical points: 512 threads per slab for a
+    // split lattice (2D L = 4096: 10.0 ms per update against 11.2 with 256,
+    // 10.5 with 1024; 3D L = 256: 0.34 ms against 0.41); one slab: 128 up
+    // to 16384 spins (2D L = 32: 30 us against 35 with 64), 256 below 2^18,
+    // 512 above (2D L = 1024: 1.46 ms against 1.70 with 256)
+    p.wg = lg.G > 1u ? 512 : N <= 16384 ? 128 : N < (1u << 18) ? 256 : 512;
     uint32_t cap = 64u;
     const uint64_t need = 2ull * (dim == 2 ? L : (uint64_t)L * L);  // bonds into a slab
     while (cap < need) cap <<= 1;
