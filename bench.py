@@ -484,11 +484,19 @@ def stats_counts(binding, workloads):
                 "atomic_bytes_per_added_spin": c["atomic_bytes"] / sites,
                 "philox_blocks_per_added_spin": c["philox"] / sites,
                 "steps_per_update": c["steps"] / max(c["updates"], 1),
-                "messages_per_added_spin": c["messages"] / sites}
+                "messages_per_added_spin": c["messages"] / sites,
+                # LDS path, thread 0 of each workgroup: shader cycles per growth step
+                "cycles_per_step": c["cycles_grow"] / max(c["steps"], 1),
+                "cycles_expand_per_step": c["cycles_expand"] / max(c["steps"], 1),
+                "cycles_publish_per_step": c["cycles_publish"] / max(c["steps"], 1),
+                "idle_to_grow_cycles": c["cycles_idle"] / max(c["cycles_grow"], 1)}
 
     for dim, L, T, seed, warm, n in [(2, 4096, workloads.TC_2D, 2, 1000, 40),
-                                     (3, 256, workloads.T_3D, 3, 3000, 200)]:
+                                     (3, 256, workloads.T_3D, 3, 3000, 200),
+                                     (2, 32, workloads.TC_2D, 1, 300, 2000)]:
         for name, path in (("default", None), ("team", binding.PATH_TEAM)):
+            if L < 64 and path is not None:
+                continue
             sim = binding.Simulation(dim, L, 1.0, T, seed)
             sim.set_spins(ordered_start(L ** dim), 0)
             sim.run(warm)
@@ -509,8 +517,10 @@ def stats_counts(binding, workloads):
             r["added"] = int(rec["csize"].sum())
             out["%dd_L%d_%s" % (dim, L, name)] = r
             log("stats %dD L=%d %s (path %d): %.1f B touched / added spin, %.2f Philox blocks, "
-                "%.0f steps / update" % (dim, L, name, path_used, r["bytes_touched_per_added_spin"],
-                                         r["philox_blocks_per_added_spin"], r["steps_per_update"]))
+                "%.0f steps / update, %.0f cycles / step (expand %.0f, publish %.0f)"
+                % (dim, L, name, path_used, r["bytes_touched_per_added_spin"],
+                   r["philox_blocks_per_added_spin"], r["steps_per_update"], r["cycles_per_step"],
+                   r["cycles_expand_per_step"], r["cycles_publish_per_step"]))
     for dim, L, warm, n in [(2, 4096, 100, 8), (3, 256, 1000, 40)]:
         jobs = workloads.same_shape_jobs(dim, L, 64, warm + n)
         b = binding.Batch(jobs, start=1)

@@ -338,6 +338,10 @@ int wolff_profile_read(wolff_sim *s, double *grow_ms, uint64_t *grow_launches,
 #define WOLFF_STAT_IDLE_POLLS     11  /* polls of a workgroup waiting for work          */
 #define WOLFF_STAT_CYCLES_GROW    12  /* LDS path: thread-0 shader cycles in growth     */
 #define WOLFF_STAT_CYCLES_IDLE    13  /* LDS path: thread-0 shader cycles polling idle  */
+#define WOLFF_STAT_CYCLES_EXPAND  14  /* LDS path: thread-0 cycles from a step's start to
+                                         its compaction (reads, Philox, claims)          */
+#define WOLFF_STAT_CYCLES_PUBLISH 15  /* LDS path: thread-0 cycles in compaction,
+                                         messages and append, end barrier included       */
 #define WOLFF_STAT_COUNT          16
 int wolff_stats_read(wolff_sim *s, uint64_t *out, int n, int reset);
 

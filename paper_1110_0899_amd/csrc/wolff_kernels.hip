@@ -870,15 +870,21 @@ __device__ __forceinline__ void run_rep(Rep* R, uint32_t max_updates, uint64_t b
 // advanced by one workgroup per launch, so its claims need no device-scope
 // atomics (they are settled in LDS); the kernel boundary publishes its state
 // to the next launch.
-// Waves per SIMD the 512- and 1024-thread batched kernels are compiled for
-// (0: as many as their registers allow).
-#ifndef WOLFF_BATCH_WAVES
-#define WOLFF_BATCH_WAVES 0
-#endif
+// The 512-thread kernels that take simple-cubic lattices are held to four
+// waves per SIMD (128 VGPRs, a few spilled), so that two workgroups share a
+// CU: on MI355X 3D L = 256 x 2048 replicas ran 14 % faster than at the 142
+// VGPRs (three waves per SIMD, one workgroup per CU) the compiler picks by
+// itself.  The square-lattice kernel fits four waves as it is (the bound
+// made it 3 % slower).
+template <int WG, int DIMS>
+constexpr int batch_waves_per_eu()
+{
+    return (WG == 512 && DIMS != 2) ? 4 : 1;
+}
 
 template <int WG, int DIMS>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(
-    (WG >= 512 && WOLFF_BATCH_WAVES > 0) ? WOLFF_BATCH_WAVES : 1))) void batch_kernel(Rep* reps, const uint32_t* order,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(batch_waves_per_eu<WG, DIMS>())))
+void batch_kernel(Rep* reps, const uint32_t* order,
                                                    uint32_t n_reps, uint32_t* next,
                                                    uint32_t max_updates, uint32_t qmask,
                                                    uint64_t budget)

@@ -491,6 +491,10 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
         const uint32_t owner = lg.dslab.div(srow);
         uint32_t head = 0u, tail = 0u, ovn = 0u;
         uint32_t claims = 0u, nstep = 0u;
+        // thread 0: an inbox-tail read issued during an earlier step, published
+        // at the start of a later one (so that no step waits for it)
+        uint32_t pend_tail = 0u;
+        bool pend_ok = false;
         if (tid == 0 && g == 0u) st.add(WOLFF_STAT_UPDATES, 1u);
         if (g == owner) {
             if (tid == 0) {
@@ -553,6 +557,7 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
                             it = ld_agent(&a.inbox_tail[g]);
                         }
                         sh[3] = it;
+                        pend_ok = false;                          // older than what was just read
                         sh[4] = fin;
                         st.add(WOLFF_STAT_IDLE_POLLS, polls + 1u);
                         st.add(WOLFF_STAT_READ_BYTES, 4u + 12u * (polls + 1u));
@@ -641,9 +646,16 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
             // chain is one block long instead of 1 + d.
             const uint32_t b0 = sh[1];
             const bool look = G > 1u && (nstep++ & 3u) == 0u;
-            uint32_t it_async = 0u;
-            if (look && tid == 0) it_async = ld_agent(&a.inbox_tail[g]);   // used at the end of the step
+            if (G > 1u && tid == 0 && pend_ok) {
+                sh[3] = pend_tail;                                // read one or more steps ago
+                pend_ok = false;
+            }
+            if (look && tid == 0) {
+                pend_tail = ld_agent(&a.inbox_tail[g]);
+                pend_ok = true;
+            }
             const uint64_t c_step = (WOLFF_STATS && tid == 0) ? clock64() : 0u;
+            uint64_t c_pub = c_step;
             if (tid == 0) st.add(WOLFF_STAT_STEPS, 1u);
             if (look && tid == 0) st.add(WOLFF_STAT_READ_BYTES, 4u);
             if (avail <= BOND_SITES) {
@@ -676,6 +688,7 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
                 st.add(WOLFF_STAT_PHILOX, elig ? 1u : 0u);
                 st.add(WOLFF_STAT_CLAIMS, (act && local) ? 1u : 0u);
                 if (tid == 0) st.add(WOLFF_STAT_STEPS_NARROW, 1u);
+                if (WOLFF_STATS && tid == 0) c_pub = clock64();
                 lds_publish<WG, 1>(a, ctl, q, wave_cnt, wave_snd, sh, ov, won, snd, to_next, nb1, nproc,
                                    epoch, b0, gprev, gnext, G, QC, head, tail, ovn, claims, st);
             } else {
@@ -737,12 +750,17 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
                     st.add(WOLFF_STAT_PHILOX, nblk);
                     st.add(WOLFF_STAT_CLAIMS, nc);
                 }
+                if (WOLFF_STATS && tid == 0) c_pub = clock64();
                 lds_publish<WG, D2>(a, ctl, q, wave_cnt, wave_snd, sh, ov, won, snd, to_next, nb, nproc,
                                     epoch, b0, gprev, gnext, G, QC, head, tail, ovn, claims, st);
             }
-            if (look && tid == 0) sh[3] = it_async;
-            if (WOLFF_STATS && tid == 0) st.add(WOLFF_STAT_CYCLES_GROW, clock64() - c_step);
             __syncthreads();
+            if (WOLFF_STATS && tid == 0) {
+                const uint64_t c_end = clock64();
+                st.add(WOLFF_STAT_CYCLES_GROW, c_end - c_step);
+                st.add(WOLFF_STAT_CYCLES_EXPAND, c_pub - c_step);
+                st.add(WOLFF_STAT_CYCLES_PUBLISH, c_end - c_pub);
+            }
         }
 
         // ---- step (v): the record of update t

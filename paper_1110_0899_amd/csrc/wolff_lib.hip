@@ -1305,11 +1305,12 @@ struct BatchLdsClass {
     size_t lds_bytes = 0;
 };
 
-// LDS classes of the batched LDS path: slabs of at most 32 KiB (square
-// lattices up to L = 512, simple-cubic up to L = 64; several workgroups
-// per CU) and the rest of the one-workgroup lattices (up to 128 KiB, one
-// workgroup per CU).  -1: not on the LDS path (Potts, or more than 2^20
-// spins).
+// LDS classes of the batched LDS path: slabs of at most 8 KiB (square
+// lattices up to L = 256, simple-cubic up to L = 32; 256-thread
+// workgroups, several per CU) and the rest of the one-workgroup lattices
+// (up to 128 KiB, 512-thread workgroups, one per CU: the mixed replica
+// set's heaviest replicas are square L = 512 near T = 2).  -1: not on the
+// LDS path (Potts, or more than 2^20 spins).
 static constexpr uint32_t BATCH_LDS_RING = 2048;
 static int batch_lds_class(const wolff_job& j, wolff::LdsGeo* geo)
 {
@@ -1317,7 +1318,7 @@ static int batch_lds_class(const wolff_job& j, wolff::LdsGeo* geo)
     LdsPlan p;
     if (!lds_plan(j.dim, (uint32_t)j.L, LDS_SLAB_BITS, &p) || p.lg.G != 1u) return -1;
     *geo = p.lg;
-    return p.lg.slab_words <= 8192u ? 0 : 1;
+    return p.lg.slab_words <= 2048u ? 0 : 1;
 }
 
 static size_t batch_lds_bytes_for(const wolff::LdsGeo& g)
@@ -1920,7 +1921,7 @@ extern "C" int wolff_server_create(uint64_t hbm_budget_bytes, int max_slots, wol
     for (int c = 0; c < 2; ++c) {
         // the mixed-dimension kernels, with the LDS of each class's largest lattice
         const int wg = c == 0 ? 256 : 512;
-        const size_t bytes = ((size_t)(c == 0 ? 8192u : 32768u) + BATCH_LDS_RING) * sizeof(uint32_t);
+        const size_t bytes = ((size_t)(c == 0 ? 2048u : 32768u) + BATCH_LDS_RING) * sizeof(uint32_t);
         const void* fn = reinterpret_cast<const void*>(lds_batch_fn(wg, 0));
         SRV_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
         int per_cu = 0;
@@ -2041,7 +2042,7 @@ static int server_split_quantum(wolff_server* v, uint32_t n, uint64_t budget)
         } else {
             const int c = part - 1;
             const int wg = c == 0 ? 256 : 512;
-            const size_t bytes = ((size_t)(c == 0 ? 8192u : 32768u) + BATCH_LDS_RING) * sizeof(uint32_t);
+            const size_t bytes = ((size_t)(c == 0 ? 2048u : 32768u) + BATCH_LDS_RING) * sizeof(uint32_t);
             hipLaunchKernelGGL(wolff::reset_counter_kernel, dim3(1), dim3(64), 0, st, next);
             hipLaunchKernelGGL(lds_batch_fn(wg, 0), dim3(cnt[part]), dim3(wg), bytes, st, v->d_reps,
                                v->d_geos, d_list, cnt[part], next, 0u, BATCH_LDS_RING - 1u, budget);

@@ -186,8 +186,8 @@ def test_special_cases():
 @pytest.mark.parametrize("lds", [True, False])
 def test_batch_matches_alone(lds):
     # lds: these lattices run on the batched LDS path, in both LDS-size
-    # classes (the square L = 600 and cubic L = 70 lattices need more than
-    # 32 KiB of LDS); off: all on the one-workgroup kernel
+    # classes (square L = 600 and cubic L = 70 need more than 8 KiB
+    # of LDS); off: all on the one-workgroup kernel
     jobs = [workloads.Job(2, 32, TC2, 11, 400), workloads.Job(3, 8, T3, 12, 300),
             workloads.Job(2, 17, 2.5, 13, 350), workloads.Job(2, 128, 2.0, 14, 60),
             workloads.Job(3, 5, 4.0, 15, 500), workloads.Job(2, 2, 1.0, 16, 100),
