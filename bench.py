@@ -70,10 +70,15 @@ def counter_summary(kernel: str, workload: str):
     return d
 
 
-def counter_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the counter summary (else None)."""
+def counter_traffic(kernel: str, workload: str, added_per_launch: float):
+    """HBM bytes per launch of this run from the counter summary (else None):
+    its bytes per added spin times the spins this run's launches add (a
+    launch runs as many updates as fit its work budget, so launches of the
+    counter run and of this run can differ in size)."""
     d = counter_summary(kernel, workload)
-    return None if d is None else d.get("hbm_bytes_per_launch")
+    if d is None or not d.get("hbm_bytes_per_added_spin"):
+        return None
+    return d["hbm_bytes_per_added_spin"] * added_per_launch
 
 
 def ordered_start(n_sites: int) -> np.ndarray:
@@ -489,13 +494,16 @@ def stats_counts(binding, workloads):
                 "cycles_per_step": c["cycles_grow"] / max(c["steps"], 1),
                 "cycles_expand_per_step": c["cycles_expand"] / max(c["steps"], 1),
                 "cycles_publish_per_step": c["cycles_publish"] / max(c["steps"], 1),
+                "send_steps_fraction": c["steps_send"] / max(c["steps"], 1),
+                "cycles_send_per_send_step": c["cycles_send"] / max(c["steps_send"], 1),
                 "idle_to_grow_cycles": c["cycles_idle"] / max(c["cycles_grow"], 1)}
 
     for dim, L, T, seed, warm, n in [(2, 4096, workloads.TC_2D, 2, 1000, 40),
                                      (3, 256, workloads.T_3D, 3, 3000, 200),
+                                     (2, 1024, workloads.TC_2D, 4, 300, 200),
                                      (2, 32, workloads.TC_2D, 1, 300, 2000)]:
         for name, path in (("default", None), ("team", binding.PATH_TEAM)):
-            if L < 64 and path is not None:
+            if L < 4096 and L != 256 and path is not None:
                 continue
             sim = binding.Simulation(dim, L, 1.0, T, seed)
             sim.set_spins(ordered_start(L ** dim), 0)
@@ -517,10 +525,12 @@ def stats_counts(binding, workloads):
             r["added"] = int(rec["csize"].sum())
             out["%dd_L%d_%s" % (dim, L, name)] = r
             log("stats %dD L=%d %s (path %d): %.1f B touched / added spin, %.2f Philox blocks, "
-                "%.0f steps / update, %.0f cycles / step (expand %.0f, publish %.0f)"
+                "%.0f steps / update, %.0f cycles / step (expand %.0f, publish %.0f; %.0f %% of "
+                "steps send, %.0f cycles waiting for message credit per send step)"
                 % (dim, L, name, path_used, r["bytes_touched_per_added_spin"],
                    r["philox_blocks_per_added_spin"], r["steps_per_update"], r["cycles_per_step"],
-                   r["cycles_expand_per_step"], r["cycles_publish_per_step"]))
+                   r["cycles_expand_per_step"], r["cycles_publish_per_step"],
+                   100.0 * r["send_steps_fraction"], r["cycles_send_per_send_step"]))
     for dim, L, warm, n in [(2, 4096, 100, 8), (3, 256, 1000, 40)]:
         jobs = workloads.same_shape_jobs(dim, L, 64, warm + n)
         b = binding.Batch(jobs, start=1)
@@ -696,11 +706,12 @@ def main():
     achieved = main_leg["grow_GBs_algorithmic"]
     kernel, path_desc = {
         binding.PATH_TEAM: ("team_kernel", "multi-workgroup team kernel"),
-        binding.PATH_LDS: ("lds_kernel", "LDS-resident lattice, 16 slabs of 256 rows"),
+        binding.PATH_LDS: ("lds_kernel", "LDS-resident lattice, 16 slabs of 256 rows, 512 threads each"),
         binding.PATH_SINGLE: ("batch_kernel", "one-workgroup kernel"),
     }[main_leg["path"]]
     # committed counters of that kernel at this workload, if taken on the current sources
-    traffic = counter_traffic(kernel, "2d_L4096")
+    added_per_launch = main_leg["added"] / max(main_leg["grow_launches"], 1)
+    traffic = counter_traffic(kernel, "2d_L4096", added_per_launch)
     out = {
         "metric": "added spins/s at Tc, 2D L=4096 & 3D L=256; % HBM peak; batched vs plain",
         "value": main_leg["added_per_s"],
@@ -738,6 +749,9 @@ def main():
             "bytes_per_added_spin": BYTES_PER_ADDED[2],
             "launches": main_leg["grow_launches"],
             "avg_launch_ms": main_leg["grow_ms"] / max(main_leg["grow_launches"], 1),
+            "added_per_launch": added_per_launch,
+            "traffic_bytes_per_added_spin": (None if traffic is None
+                                             else traffic / max(added_per_launch, 1.0)),
         },
         "cpu_baseline": cpu,
         "extra": extra,

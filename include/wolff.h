@@ -342,7 +342,11 @@ int wolff_profile_read(wolff_sim *s, double *grow_ms, uint64_t *grow_launches,
                                          its compaction (reads, Philox, claims)          */
 #define WOLFF_STAT_CYCLES_PUBLISH 15  /* LDS path: thread-0 cycles in compaction,
                                          messages and append, end barrier included       */
-#define WOLFF_STAT_COUNT          16
+#define WOLFF_STAT_STEPS_SEND     16  /* LDS path: steps that sent messages             */
+#define WOLFF_STAT_CYCLES_SEND    17  /* LDS path: thread-0 cycles steps waited for
+                                         their message credit to be added to the
+                                         team's outstanding-work counter                */
+#define WOLFF_STAT_COUNT          18
 int wolff_stats_read(wolff_sim *s, uint64_t *out, int n, int reset);
 
 /* Static description of an error code (never NULL).  (Plumbing: no

@@ -81,8 +81,8 @@ JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 # WOLFF_STAT_* counters of the counting build, in index order
 STAT_NAMES = ["updates", "sites", "steps", "steps_narrow", "neighbour_reads", "philox", "claims",
               "read_bytes", "write_bytes", "atomic_bytes", "messages", "idle_polls", "cycles_grow",
-              "cycles_idle", "cycles_expand", "cycles_publish"]
-STAT_COUNT = 16
+              "cycles_idle", "cycles_expand", "cycles_publish", "steps_send", "cycles_send"]
+STAT_COUNT = 18
 
 RECORD_DTYPE = np.dtype([("bond_sum", np.int64), ("mag", np.int64), ("csize", np.int64)])
 

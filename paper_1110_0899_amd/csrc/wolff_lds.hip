@@ -21,12 +21,23 @@
 // neighbours whose bond is active with an LDS atomic OR / AND that flips the
 // bit (exactly one caller sees the old bit equal to the seed spin s0), and
 // sends a message (site, s0) for every active bond whose far site is in
-// another slab; the receiver claims it if its spin is s0.  A device-scope
-// counter P = (t + 1) << 32 | outstanding units (claimed sites not yet
-// expanded plus messages not yet consumed) decides when the cluster is
-// complete: a workgroup adds its net change once per step, and a step that
-// sends messages waits for its addition to be performed before the messages
-// become visible, so P never reaches 0 while work is left.  After P reaches
+// another slab; the receiver claims it if its spin is s0.  Messages travel
+// on single-producer rings: slab g reads one ring filled by slab g - 1 and
+// one filled by slab g + 1, so a sender places its messages at counters it
+// keeps itself (no slot reservation) and then publishes the ring's new end
+// with a plain store; entries carry the update index, so a receiver that
+// reads an end before the entries below it simply waits for their tags.
+// A device-scope counter P = (t + 1) << 32 | outstanding units decides when
+// the cluster is complete.  The units are claimed sites not yet expanded,
+// messages not yet consumed, and credit: before a step that could send more
+// messages than its workgroup's remaining credit, the workgroup adds a block
+// of credit to P (the addition issued at the step's start and waited for
+// before the step's messages are written, so its latency hides behind the
+// expansion); a message spends one unit of credit, the receiver removes it
+// when it consumes the message, and a workgroup that runs out of work hands
+// its unspent credit back.  Every other change (sites claimed minus sites
+// expanded) is added once per step without waiting, so P never reaches 0
+// while work or a message is left.  After P reaches
 // 0 the team counts the bond sum (every slab its rows plus the rows it
 // shares with the next slab, whose first row each slab publishes) and its
 // negative spins, and the last workgroup at the update's grid barrier writes
@@ -73,8 +84,10 @@ struct LdsCtl {
 struct LdsArgs {
     Rep* R;
     LdsCtl* ctl;
-    unsigned long long* inbox;     // G rings of imask + 1 entries
-    uint32_t* inbox_tail;          // G counters (slots reserved so far)
+    unsigned long long* inbox;     // 2G message rings of imask + 1 entries: ring 2g + 0 is
+                                   // filled by slab g - 1, ring 2g + 1 by slab g + 1
+    uint32_t* inbox_tail;          // 2G counters: entries written to each ring so far (each
+                                   // stored only by the ring's one sender; 8-byte aligned)
     uint32_t imask;
     uint32_t* bnd;                 // G * bnd_words: first row (2D) / plane (3D) of every slab
     uint32_t bnd_words;
@@ -100,6 +113,17 @@ __device__ __forceinline__ uint32_t ld_agent(const uint32_t* p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, SCOPE_AGENT);
 }
+// The ends of the two message rings slab g reads, in one load: ring 2g + 0
+// (filled by slab g - 1) in the low word, ring 2g + 1 in the high word.
+__device__ __forceinline__ uint64_t ld_tails(const uint32_t* tails, uint32_t g)
+{
+    return __hip_atomic_load(reinterpret_cast<const unsigned long long*>(tails + 2u * g),
+                             __ATOMIC_RELAXED, SCOPE_AGENT);
+}
+// Units of P a workgroup of WG threads adds at a time as message credit: at
+// least what one step can spend (two far neighbours per site at most).
+template <int WG>
+constexpr uint32_t credit_block() { return 4u * (uint32_t)WG; }
 
 __device__ __forceinline__ void flag_wait_failure(LdsCtl* ctl)
 {
@@ -280,7 +304,9 @@ __device__ __forceinline__ void lds_publish(const LdsArgs& a, LdsCtl* ctl, uint3
                                             const uint32_t nb[NS], uint32_t nproc,
                                             unsigned long long epoch, uint32_t b0, uint32_t gprev,
                                             uint32_t gnext, uint32_t G, uint32_t QC, uint32_t& head,
-                                            uint32_t& tail, uint32_t& ovn, uint32_t& claims, StatAcc& st)
+                                            uint32_t& tail, uint32_t& ovn, uint32_t& claims,
+                                            uint32_t& cprev, uint32_t& cnext, uint32_t& credit,
+                                            StatAcc& st)
 {
     constexpr int NW = WG / WAVE;
     const uint32_t tid = threadIdx.x;
@@ -326,35 +352,39 @@ __device__ __forceinline__ void lds_publish(const LdsArgs& a, LdsCtl* ctl, uint3
         }
     }
     if (G > 1u) {
-        if (tid == 0) {
-            const long long delta = (long long)total + (long long)(ptot + ntot) - (long long)nproc;
-            if (ptot + ntot > 0u) {
-                // the units of the messages must be in P before a
-                // receiver can consume them: wait for the addition
-                sh[7] = (uint32_t)__hip_atomic_fetch_add(&ctl->P, (unsigned long long)delta,
-                                                         __ATOMIC_RELAXED, SCOPE_AGENT);
-                sh[5] = ptot ? __hip_atomic_fetch_add(&a.inbox_tail[gprev], ptot, __ATOMIC_RELAXED, SCOPE_AGENT) : 0u;
-                sh[6] = ntot ? __hip_atomic_fetch_add(&a.inbox_tail[gnext], ntot, __ATOMIC_RELAXED, SCOPE_AGENT) : 0u;
-                st.add(WOLFF_STAT_ATOMIC_BYTES, 8u + (ptot ? 4u : 0u) + (ntot ? 4u : 0u));
-            } else if (delta != 0) {
-                __hip_atomic_fetch_add(&ctl->P, (unsigned long long)delta, __ATOMIC_RELAXED, SCOPE_AGENT);
-                st.add(WOLFF_STAT_ATOMIC_BYTES, 8u);
-            }
-        }
+        // the messages go to the two rings this workgroup alone fills, at
+        // the counters every thread keeps (the same in all); their units
+        // come out of the credit already in P (thread 0 waited for the
+        // credit's addition before the barrier above)
         if (ptot + ntot > 0u) {
-            __syncthreads();
-            const uint32_t basep = sh[5], basen = sh[6];
             const unsigned long long word = epoch | (b0 ? MSG_S0_NEG : 0u);
+            const uint32_t QI = a.imask + 1u;
 #pragma unroll
             for (int m = 0; m < NS; ++m) {
                 if (snd[m]) {
-                    const uint32_t dst = to_next[m] ? gnext : gprev;
-                    const uint32_t slot = to_next[m] ? basen + nbf + spos[m] : basep + pb + spos[m];
-                    __hip_atomic_store(&a.inbox[(size_t)dst * (a.imask + 1u) + (slot & a.imask)],
-                                       word | nb[m], __ATOMIC_RELAXED, SCOPE_AGENT);
+                    const size_t ring = to_next[m] ? 2u * (size_t)gnext : 2u * (size_t)gprev + 1u;
+                    const uint32_t slot = to_next[m] ? cnext + nbf + spos[m] : cprev + pb + spos[m];
+                    __hip_atomic_store(&a.inbox[ring * QI + (slot & a.imask)], word | nb[m],
+                                       __ATOMIC_RELAXED, SCOPE_AGENT);
                     st.add(WOLFF_STAT_WRITE_BYTES, 8u);
                     st.add(WOLFF_STAT_MESSAGES, 1u);
                 }
+            }
+            cprev += ptot;
+            cnext += ntot;
+            if (tid == 0) {
+                if (ptot) __hip_atomic_store(&a.inbox_tail[2u * gprev + 1u], cprev, __ATOMIC_RELAXED, SCOPE_AGENT);
+                if (ntot) __hip_atomic_store(&a.inbox_tail[2u * gnext], cnext, __ATOMIC_RELAXED, SCOPE_AGENT);
+                st.add(WOLFF_STAT_WRITE_BYTES, (ptot ? 4u : 0u) + (ntot ? 4u : 0u));
+                st.add(WOLFF_STAT_STEPS_SEND, 1u);
+            }
+        }
+        if (tid == 0) {
+            credit -= ptot + ntot;
+            const long long delta = (long long)total - (long long)nproc;
+            if (delta != 0) {
+                __hip_atomic_fetch_add(&ctl->P, (unsigned long long)delta, __ATOMIC_RELAXED, SCOPE_AGENT);
+                st.add(WOLFF_STAT_ATOMIC_BYTES, 8u);
             }
         }
     }
@@ -379,13 +409,23 @@ __device__ __forceinline__ void lds_publish(const LdsArgs& a, LdsCtl* ctl, uint3
     claims += total;
 }
 
+// Thread 0, before the barrier that precedes a step's messages: the credit
+// added at the step's start must have been performed (its returned value is
+// used, so the wave waits for it).
+__device__ __forceinline__ void credit_wait(uint32_t* sh, unsigned long long ret, uint64_t c0,
+                                            StatAcc& st)
+{
+    sh[10] = (uint32_t)ret;
+    if (WOLFF_STATS) st.add(WOLFF_STAT_CYCLES_SEND, clock64() - c0);
+}
+
 // Workgroup-shared words of the LDS path beside the slab and the ring.
 template <int NW>
 struct LdsShm {
     uint32_t wave_cnt[NW];
     uint32_t wave_snd[2 * NW];
     uint64_t red[2 * NW];
-    uint32_t sh[8];
+    uint32_t sh[12];
 };
 
 // All updates of one lattice (up to max_updates, or until the wall-clock
@@ -430,7 +470,7 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
     const uint32_t gprev = (g == 0u) ? G - 1u : g - 1u;
     const uint32_t gnext = (g + 1u == G) ? 0u : g + 1u;
     gword* ov = as_global(a.ov + (size_t)g * a.ov_stride);
-    unsigned long long* inbox = a.inbox + (size_t)g * (a.imask + 1u);
+    const unsigned long long* inbox = a.inbox + 2u * (size_t)g * (a.imask + 1u);
     const gbyte* SG = as_global(R->S);
 
     // the slab from the int8 lattice (any storage order; bit 1 of a byte is
@@ -448,11 +488,14 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
         }
         bits[w] = v;
     }
-    uint32_t ihead = 0u;
     if (tid == 0) {
-        ihead = G > 1u ? ld_agent(&a.inbox_tail[g]) : 0u;     // every message was consumed
-        sh[0] = ihead;
-        sh[3] = ihead;
+        // every message was consumed: the rings this slab reads start at
+        // their ends; the counters of the two rings it fills are its own
+        const uint64_t it = G > 1u ? ld_tails(a.inbox_tail, g) : 0u;
+        sh[0] = sh[3] = (uint32_t)it;
+        sh[6] = sh[7] = (uint32_t)(it >> 32);
+        sh[8] = G > 1u ? ld_agent(&a.inbox_tail[2u * gnext]) : 0u;
+        sh[9] = G > 1u ? ld_agent(&a.inbox_tail[2u * gprev + 1u]) : 0u;
     }
     // a stop request seen before the first update: run none
     if (MULTI) {
@@ -469,7 +512,9 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
         if (tid == 0) sh[5] = abort_requested(R->abort);
     }
     __syncthreads();
-    ihead = sh[0];
+    uint32_t ihead0 = sh[0], ihead1 = sh[6];          // next entries to read, by ring
+    uint32_t cnext = sh[8], cprev = sh[9];            // entries written to the rings filled
+    uint32_t credit = 0u;                             // thread 0: units of P not yet spent
     if (sh[5]) n = 0u;
     const uint64_t rec0 = R->rec_count;
     __syncthreads();
@@ -491,10 +536,12 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
         const uint32_t owner = lg.dslab.div(srow);
         uint32_t head = 0u, tail = 0u, ovn = 0u;
         uint32_t claims = 0u, nstep = 0u;
-        // thread 0: an inbox-tail read issued during an earlier step, published
-        // at the start of a later one (so that no step waits for it)
-        uint32_t pend_tail = 0u;
-        bool pend_ok = false;
+        // thread 0: a read of the ring ends issued at the start of a step and
+        // published at the end of the next one (so that no step waits for
+        // it; a publication needs the barrier that ends a step)
+        uint64_t pend_tail = 0u;
+        bool pend_ok = false, pend_new = false;
+        credit = 0u;
         if (tid == 0 && g == 0u) st.add(WOLFF_STAT_UPDATES, 1u);
         if (g == owner) {
             if (tid == 0) {
@@ -530,20 +577,27 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
             // messages from the other slabs: while the workgroup has work of
             // its own it looks at its inbox through the tail read (without
             // waiting) during every fourth step; idle, it polls the inbox and P
-            uint32_t itail = ihead;
+            uint32_t itail0 = ihead0, itail1 = ihead1;
             if (G > 1u) {
                 if (avail == 0u) {
                     if (tid == 0) {
                         const uint64_t c_idle = WOLFF_STATS ? clock64() : 0u;
-                        uint32_t it = ld_agent(&a.inbox_tail[g]);
+                        if (credit) {                             // out of work: hand the credit back
+                            __hip_atomic_fetch_add(&ctl->P, (unsigned long long)(0ll - (long long)credit),
+                                                   __ATOMIC_RELAXED, SCOPE_AGENT);
+                            st.add(WOLFF_STAT_ATOMIC_BYTES, 8u);
+                            credit = 0u;
+                        }
+                        const uint64_t ih = ((uint64_t)ihead1 << 32) | ihead0;
+                        uint64_t it = ld_tails(a.inbox_tail, g);
                         uint32_t fin = 0u;
                         uint32_t polls = 0u, backoff = 1u;
-                        while (it == ihead) {
+                        while (it == ih) {
                             const unsigned long long p = ld_agent(&ctl->P);
                             if ((p >> 32) > (epoch >> 32) || p == epoch) {
                                 // P reached 0: every message was consumed
-                                it = ld_agent(&a.inbox_tail[g]);
-                                fin = it == ihead ? 1u : 0u;
+                                it = ld_tails(a.inbox_tail, g);
+                                fin = it == ih ? 1u : 0u;
                                 break;
                             }
                             if (++polls > LDS_SPIN_LIMIT ||
@@ -554,38 +608,48 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
                             }
                             for (uint32_t b = 0; b < backoff; ++b) __builtin_amdgcn_s_sleep(1);
                             if (backoff < 8u) backoff <<= 1;
-                            it = ld_agent(&a.inbox_tail[g]);
+                            it = ld_tails(a.inbox_tail, g);
                         }
-                        sh[3] = it;
+                        sh[3] = (uint32_t)it;
+                        sh[7] = (uint32_t)(it >> 32);
                         pend_ok = false;                          // older than what was just read
                         sh[4] = fin;
                         st.add(WOLFF_STAT_IDLE_POLLS, polls + 1u);
-                        st.add(WOLFF_STAT_READ_BYTES, 4u + 12u * (polls + 1u));
+                        st.add(WOLFF_STAT_READ_BYTES, 8u + 16u * (polls + 1u));
                         if (WOLFF_STATS) st.add(WOLFF_STAT_CYCLES_IDLE, clock64() - c_idle);
                     }
                     __syncthreads();
                     const uint32_t fin = sh[4];
-                    itail = sh[3];
+                    itail0 = sh[3];
+                    itail1 = sh[7];
                     __syncthreads();
                     if (fin) break;
                 } else {
-                    itail = sh[3];                                // the latest tail read (may lag)
+                    itail0 = sh[3];                               // the latest reads (may lag)
+                    itail1 = sh[7];
                 }
             } else if (avail == 0u) {
                 break;                                            // one workgroup: the cluster is complete
             }
 
-            if (itail != ihead) {
-                // claim the sites of up to WG messages (the sender found the bond active)
-                const uint32_t m = min(itail - ihead, (uint32_t)WG);
+            if (itail0 != ihead0 || itail1 != ihead1) {
+                // claim the sites of up to WG messages (the sender found the
+                // bond active): lanes [0, m0) read ring 2g + 0, [m0, m0 + m1)
+                // ring 2g + 1
+                const uint32_t m0 = min(itail0 - ihead0, (uint32_t)WG);
+                const uint32_t m1 = min(itail1 - ihead1, (uint32_t)WG - m0);
+                const uint32_t m = m0 + m1;
                 bool won = false;
                 uint32_t k = 0u;
                 if (tid < m) {
-                    const unsigned long long* slot = &inbox[(ihead + tid) & a.imask];
+                    const bool r1 = tid >= m0;
+                    const uint32_t idx = r1 ? ihead1 + (tid - m0) : ihead0 + tid;
+                    const unsigned long long* slot =
+                        &inbox[(r1 ? (size_t)(a.imask + 1u) : 0u) + (idx & a.imask)];
                     unsigned long long v = ld_agent(slot);
                     uint32_t polls = 0u;
                     st.add(WOLFF_STAT_READ_BYTES, 8u);
-                    while ((v >> 32) != (epoch >> 32)) {          // reserved, not yet written
+                    while ((v >> 32) != (epoch >> 32)) {          // counted, not yet visible
                         if (++polls > LDS_SPIN_LIMIT) {
                             flag_wait_failure(ctl);
                             break;
@@ -624,7 +688,8 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
                     ovn += total;
                 }
                 claims += total;
-                ihead += m;
+                ihead0 += m0;
+                ihead1 += m1;
                 if (tid == 0) {
                     sh[2] = 1u;
                     const long long delta = (long long)total - (long long)m;
@@ -646,18 +711,25 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
             // chain is one block long instead of 1 + d.
             const uint32_t b0 = sh[1];
             const bool look = G > 1u && (nstep++ & 3u) == 0u;
-            if (G > 1u && tid == 0 && pend_ok) {
-                sh[3] = pend_tail;                                // read one or more steps ago
-                pend_ok = false;
-            }
             if (look && tid == 0) {
-                pend_tail = ld_agent(&a.inbox_tail[g]);
-                pend_ok = true;
+                pend_tail = ld_tails(a.inbox_tail, g);
+                pend_ok = pend_new = true;
+            }
+            // message credit for this step, added now and waited for just
+            // before the step's messages are written
+            unsigned long long credit_ret = 0u;
+            bool refill = false;
+            if (G > 1u && tid == 0 && credit < 2u * min(avail, (uint32_t)WG)) {
+                credit_ret = __hip_atomic_fetch_add(&ctl->P, (unsigned long long)credit_block<WG>(),
+                                                    __ATOMIC_RELAXED, SCOPE_AGENT);
+                credit += credit_block<WG>();
+                refill = true;
+                st.add(WOLFF_STAT_ATOMIC_BYTES, 8u);
             }
             const uint64_t c_step = (WOLFF_STATS && tid == 0) ? clock64() : 0u;
             uint64_t c_pub = c_step;
             if (tid == 0) st.add(WOLFF_STAT_STEPS, 1u);
-            if (look && tid == 0) st.add(WOLFF_STAT_READ_BYTES, 4u);
+            if (look && tid == 0) st.add(WOLFF_STAT_READ_BYTES, 8u);
             if (avail <= BOND_SITES) {
                 const uint32_t si = tid / (uint32_t)D2;
                 const uint32_t m = tid - si * (uint32_t)D2;
@@ -689,8 +761,10 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
                 st.add(WOLFF_STAT_CLAIMS, (act && local) ? 1u : 0u);
                 if (tid == 0) st.add(WOLFF_STAT_STEPS_NARROW, 1u);
                 if (WOLFF_STATS && tid == 0) c_pub = clock64();
+                if (refill) credit_wait(sh, credit_ret, c_pub, st);
                 lds_publish<WG, 1>(a, ctl, q, wave_cnt, wave_snd, sh, ov, won, snd, to_next, nb1, nproc,
-                                   epoch, b0, gprev, gnext, G, QC, head, tail, ovn, claims, st);
+                                   epoch, b0, gprev, gnext, G, QC, head, tail, ovn, claims,
+                                   cprev, cnext, credit, st);
             } else {
                 const uint32_t nproc = min(avail, (uint32_t)WG);
                 const bool active = tid < nproc;
@@ -751,8 +825,18 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
                     st.add(WOLFF_STAT_CLAIMS, nc);
                 }
                 if (WOLFF_STATS && tid == 0) c_pub = clock64();
+                if (refill) credit_wait(sh, credit_ret, c_pub, st);
                 lds_publish<WG, D2>(a, ctl, q, wave_cnt, wave_snd, sh, ov, won, snd, to_next, nb, nproc,
-                                    epoch, b0, gprev, gnext, G, QC, head, tail, ovn, claims, st);
+                                    epoch, b0, gprev, gnext, G, QC, head, tail, ovn, claims,
+                                    cprev, cnext, credit, st);
+            }
+            if (G > 1u && tid == 0) {
+                if (pend_ok && !pend_new) {
+                    sh[3] = (uint32_t)pend_tail;                  // read during the last step
+                    sh[7] = (uint32_t)(pend_tail >> 32);
+                    pend_ok = false;
+                }
+                pend_new = false;
             }
             __syncthreads();
             if (WOLFF_STATS && tid == 0) {

@@ -400,7 +400,7 @@ static constexpr uint32_t LDS_MAX_SLABS = 64;
 struct LdsPlan {
     wolff::LdsGeo lg;
     int wg;
-    uint32_t imask;         // inbox entries - 1
+    uint32_t imask;         // entries of one message ring - 1
     uint32_t bnd_words;
     uint32_t ov_stride;
     size_t lds_bytes;
@@ -434,8 +434,10 @@ static bool lds_plan(int dim, uint32_t L, uint32_t slab_bits, LdsPlan* out)
     // to 16384 spins (2D L = 32: 30 us against 35 with 64), 256 below 2^18,
     // 512 above (2D L = 1024: 1.46 ms against 1.70 with 256)
     p.wg = lg.G > 1u ? 512 : N <= 16384 ? 128 : N < (1u << 18) ? 256 : 512;
+    // a message ring carries the bonds across one slab boundary in one
+    // direction, each at most once per update: L^(d-1) entries
     uint32_t cap = 64u;
-    const uint64_t need = 2ull * (dim == 2 ? L : (uint64_t)L * L);  // bonds into a slab
+    const uint64_t need = dim == 2 ? L : (uint64_t)L * L;
     while (cap < need) cap <<= 1;
     p.imask = cap - 1u;
     p.bnd_words = (dim == 2 ? 1u : L) * lg.RW;
@@ -834,8 +836,8 @@ static int ensure_lds(wolff_sim* s, const LdsPlan& p)
     if (s->lctl) return WOLFF_OK;
     const uint32_t G = p.lg.G;
     HIP_TRY(hipStreamSynchronize(s->stream));
-    s->lbytes_inbox = (size_t)G * (p.imask + 1u) * sizeof(unsigned long long);
-    s->lbytes_tail = (size_t)G * sizeof(uint32_t);
+    s->lbytes_inbox = 2u * (size_t)G * (p.imask + 1u) * sizeof(unsigned long long);
+    s->lbytes_tail = 2u * (size_t)G * sizeof(uint32_t);
     HIP_TRY(hipMalloc(&s->lctl, sizeof(wolff::LdsCtl)));
     HIP_TRY(hipMalloc(&s->linbox, s->lbytes_inbox));
     HIP_TRY(hipMalloc(&s->ltail, s->lbytes_tail));

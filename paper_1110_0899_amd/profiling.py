@@ -6,8 +6,13 @@
         --last <n dispatches> --added <added spins> --out profiles/counters_<kernel>_<workload>.json \
         --command "<command>"
 
+    python -m paper_1110_0899_amd.profiling pmc --kernel lds_kernel --dir <dir> --last <n> \
+        --added <added spins> --out profiles/<name>.md --command "<command>" [--note ...]
+
 `stats` reads the kernel-trace statistics (csv or rocpd sqlite output) and
-writes a markdown table.  `counters` averages FETCH_SIZE / WRITE_SIZE (KiB
+writes a markdown table.  `pmc` sums every counter of one `--pmc` run over
+the last n dispatches of a kernel and writes them per dispatch and per added
+spin.  `counters` averages FETCH_SIZE / WRITE_SIZE (KiB
 per dispatch) over the last n dispatches of a kernel, scales each by what
 the same counter reports for the calibration copy (1 GiB read, 1 GiB
 written), and records the kernel-source hash, so that bench.py uses the
@@ -112,6 +117,33 @@ def counters(a):
     print(json.dumps(out, indent=1))
 
 
+def pmc_table(a):
+    files = glob.glob(os.path.join(a.dir, "**", "*counter_collection.csv"), recursive=True)
+    per = {}
+    for r in csv.DictReader(open(files[0])):
+        if a.kernel in r["Kernel_Name"]:
+            per.setdefault(r["Counter_Name"], []).append((int(r["Dispatch_Id"]),
+                                                          float(r["Counter_Value"])))
+    name = None
+    for r in csv.DictReader(open(files[0])):
+        if a.kernel in r["Kernel_Name"]:
+            name = r["Kernel_Name"].split("(")[0]
+            break
+    with open(a.out, "w") as f:
+        f.write("# rocprofv3 counters of `%s`\n\nCommand (repository at $R, run from a scratch "
+                "directory):\n\n    %s\n\n" % (name, a.command))
+        if a.note:
+            f.write(a.note.strip() + "\n\n")
+        f.write("Summed over the last %d dispatches (%.4g added spins).\n\n" % (a.last, a.added))
+        f.write("| counter | per dispatch | per added spin |\n|---|---|---|\n")
+        for c in sorted(per):
+            v = [x for _, x in sorted(per[c])][-a.last:]
+            tot = sum(v)
+            f.write("| `%s` | %.4g | %s |\n" % (c, tot / len(v),
+                                               "%.4g" % (tot / a.added) if a.added else "-"))
+        f.write("\nKernel sources: %s\n" % kernel_source_sha())
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -125,9 +157,17 @@ def main():
         c.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
     c.add_argument("--last", type=int, default=1)
     c.add_argument("--added", type=float, default=0.0, help="added spins over the last dispatches")
+    m = sub.add_parser("pmc")
+    for k in ("kernel", "dir", "out", "command"):
+        m.add_argument("--" + k, dest=k, required=True)
+    m.add_argument("--last", type=int, default=1)
+    m.add_argument("--added", type=float, default=0.0)
+    m.add_argument("--note", default="")
     a = ap.parse_args()
     if a.cmd == "stats":
         write_stats(a.dir, a.out, a.command, a.note)
+    elif a.cmd == "pmc":
+        pmc_table(a)
     else:
         counters(a)
 

@@ -54,13 +54,15 @@ def test_counter_summary_arithmetic(tmp_path):
 def test_stale_summary_is_ignored(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
-    good = {"kernel_source_sha": profiling.kernel_source_sha(), "hbm_bytes_per_launch": 123.0}
+    good = {"kernel_source_sha": profiling.kernel_source_sha(), "hbm_bytes_per_launch": 123.0,
+            "hbm_bytes_per_added_spin": 2.5}
     (prof / "counters_k_w.json").write_text(json.dumps(good))
     (prof / "counters_k_old.json").write_text(json.dumps(dict(good, kernel_source_sha="0" * 16)))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.counter_traffic("k", "w") == 123.0
-    assert bench.counter_traffic("k", "old") is None
-    assert bench.counter_traffic("k", "missing") is None
+    # bytes per added spin of the counter run, times this run's spins per launch
+    assert bench.counter_traffic("k", "w", 1000.0) == 2500.0
+    assert bench.counter_traffic("k", "old", 1000.0) is None
+    assert bench.counter_traffic("k", "missing", 1000.0) is None
 
 
 def test_source_hash_covers_device_code_only():
