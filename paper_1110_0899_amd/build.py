@@ -22,6 +22,10 @@ FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared", "-Wall",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # every global atomic here is issued by one lane (thread 0 or a wave's
+    # leader, sums already taken with ballots); the compiler's wave-level
+    # atomic combining would only add a scan and wait for the result at once
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
 ]
 
 

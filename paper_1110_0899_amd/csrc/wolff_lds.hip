@@ -293,10 +293,21 @@ __device__ __forceinline__ void claim_bits(uint32_t* bits, const uint32_t ba[NS]
     }
 }
 
+// Thread 0: a read of the ring ends issued at the start of a step, published
+// to the workgroup one step later, after the first barrier of that step (so
+// that no wave still reads the previous value and no wait is needed: the
+// read is a step old, and the step's own stores are not issued yet).
+struct TailRead {
+    uint64_t v;
+    bool ok;        // issued and not yet published
+    bool fresh;     // issued during the current step
+};
+
 // Second half of a growth step, for NS neighbour slots per lane: compaction
 // of the claimed sites and of the messages (to the previous / next slab),
-// the step's net change of P (before any of its messages is written), the
-// messages, and the claimed sites appended to the ring or the overflow stack.
+// publication of the ring ends read a step earlier, the messages (paid from
+// the credit), the step's net change of P in sites, and the claimed sites
+// appended to the ring or the overflow stack.
 template <int WG, int NS>
 __device__ __forceinline__ void lds_publish(const LdsArgs& a, LdsCtl* ctl, uint32_t* q, uint32_t* wave_cnt,
                                             uint32_t* wave_snd, uint32_t* sh, gword* ov, const bool won[NS],
@@ -306,7 +317,7 @@ __device__ __forceinline__ void lds_publish(const LdsArgs& a, LdsCtl* ctl, uint3
                                             uint32_t gnext, uint32_t G, uint32_t QC, uint32_t& head,
                                             uint32_t& tail, uint32_t& ovn, uint32_t& claims,
                                             uint32_t& cprev, uint32_t& cnext, uint32_t& credit,
-                                            StatAcc& st)
+                                            TailRead& tr, StatAcc& st)
 {
     constexpr int NW = WG / WAVE;
     const uint32_t tid = threadIdx.x;
@@ -350,6 +361,14 @@ __device__ __forceinline__ void lds_publish(const LdsArgs& a, LdsCtl* ctl, uint3
             ptot += cp;
             ntot += cn;
         }
+    }
+    if (G > 1u && tid == 0) {
+        if (tr.ok && !tr.fresh) {
+            sh[3] = (uint32_t)tr.v;
+            sh[7] = (uint32_t)(tr.v >> 32);
+            tr.ok = false;
+        }
+        tr.fresh = false;
     }
     if (G > 1u) {
         // the messages go to the two rings this workgroup alone fills, at
@@ -409,13 +428,18 @@ __device__ __forceinline__ void lds_publish(const LdsArgs& a, LdsCtl* ctl, uint3
     claims += total;
 }
 
+// s_waitcnt with vmcnt(0) and the other counters unconstrained (expcnt 7,
+// lgkmcnt 15).  On gfx950 vmcnt counts stores and atomics as well as loads,
+// so this waits until every global access the wave issued was performed.
+constexpr int WAITCNT_VM0 = 0x0F70;
+
 // Thread 0, before the barrier that precedes a step's messages: the credit
-// added at the step's start must have been performed (its returned value is
-// used, so the wave waits for it).
-__device__ __forceinline__ void credit_wait(uint32_t* sh, unsigned long long ret, uint64_t c0,
-                                            StatAcc& st)
+// added (without a returned value) at the step's start must have been
+// performed.  A returned value would make the compiler wait at the first
+// reuse of its register, and with it for every access issued before.
+__device__ __forceinline__ void credit_wait(uint64_t c0, StatAcc& st)
 {
-    sh[10] = (uint32_t)ret;
+    __builtin_amdgcn_s_waitcnt(WAITCNT_VM0);
     if (WOLFF_STATS) st.add(WOLFF_STAT_CYCLES_SEND, clock64() - c0);
 }
 
@@ -536,11 +560,7 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
         const uint32_t owner = lg.dslab.div(srow);
         uint32_t head = 0u, tail = 0u, ovn = 0u;
         uint32_t claims = 0u, nstep = 0u;
-        // thread 0: a read of the ring ends issued at the start of a step and
-        // published at the end of the next one (so that no step waits for
-        // it; a publication needs the barrier that ends a step)
-        uint64_t pend_tail = 0u;
-        bool pend_ok = false, pend_new = false;
+        TailRead tr{0u, false, false};
         credit = 0u;
         if (tid == 0 && g == 0u) st.add(WOLFF_STAT_UPDATES, 1u);
         if (g == owner) {
@@ -575,8 +595,11 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
                 avail = tail - head;
             }
             // messages from the other slabs: while the workgroup has work of
-            // its own it looks at its inbox through the tail read (without
-            // waiting) during every fourth step; idle, it polls the inbox and P
+            // its own it reads the ends of its two rings (without waiting)
+            // during every sixteenth step and sees the value one step later;
+            // idle, it polls the ring ends and P.  (Reading every second step, or
+            // every fourth, was measured slower on MI355X: 2D L = 4096 at T_c
+            // 8.3 and 8.1 against 7.8 ms per update.)
             uint32_t itail0 = ihead0, itail1 = ihead1;
             if (G > 1u) {
                 if (avail == 0u) {
@@ -612,7 +635,7 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
                         }
                         sh[3] = (uint32_t)it;
                         sh[7] = (uint32_t)(it >> 32);
-                        pend_ok = false;                          // older than what was just read
+                        tr.ok = false;                            // older than what was just read
                         sh[4] = fin;
                         st.add(WOLFF_STAT_IDLE_POLLS, polls + 1u);
                         st.add(WOLFF_STAT_READ_BYTES, 8u + 16u * (polls + 1u));
@@ -710,18 +733,14 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
             // claims are spread over 2d times more lanes and the step's
             // chain is one block long instead of 1 + d.
             const uint32_t b0 = sh[1];
-            const bool look = G > 1u && (nstep++ & 3u) == 0u;
-            if (look && tid == 0) {
-                pend_tail = ld_tails(a.inbox_tail, g);
-                pend_ok = pend_new = true;
-            }
+            const bool look = G > 1u && (nstep++ & 15u) == 0u;
+            if (look && tid == 0) tr = TailRead{ld_tails(a.inbox_tail, g), true, true};
             // message credit for this step, added now and waited for just
             // before the step's messages are written
-            unsigned long long credit_ret = 0u;
             bool refill = false;
             if (G > 1u && tid == 0 && credit < 2u * min(avail, (uint32_t)WG)) {
-                credit_ret = __hip_atomic_fetch_add(&ctl->P, (unsigned long long)credit_block<WG>(),
-                                                    __ATOMIC_RELAXED, SCOPE_AGENT);
+                __hip_atomic_fetch_add(&ctl->P, (unsigned long long)credit_block<WG>(),
+                                       __ATOMIC_RELAXED, SCOPE_AGENT);
                 credit += credit_block<WG>();
                 refill = true;
                 st.add(WOLFF_STAT_ATOMIC_BYTES, 8u);
@@ -761,10 +780,10 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
                 st.add(WOLFF_STAT_CLAIMS, (act && local) ? 1u : 0u);
                 if (tid == 0) st.add(WOLFF_STAT_STEPS_NARROW, 1u);
                 if (WOLFF_STATS && tid == 0) c_pub = clock64();
-                if (refill) credit_wait(sh, credit_ret, c_pub, st);
+                if (refill) credit_wait(c_pub, st);
                 lds_publish<WG, 1>(a, ctl, q, wave_cnt, wave_snd, sh, ov, won, snd, to_next, nb1, nproc,
                                    epoch, b0, gprev, gnext, G, QC, head, tail, ovn, claims,
-                                   cprev, cnext, credit, st);
+                                   cprev, cnext, credit, tr, st);
             } else {
                 const uint32_t nproc = min(avail, (uint32_t)WG);
                 const bool active = tid < nproc;
@@ -825,18 +844,10 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
                     st.add(WOLFF_STAT_CLAIMS, nc);
                 }
                 if (WOLFF_STATS && tid == 0) c_pub = clock64();
-                if (refill) credit_wait(sh, credit_ret, c_pub, st);
+                if (refill) credit_wait(c_pub, st);
                 lds_publish<WG, D2>(a, ctl, q, wave_cnt, wave_snd, sh, ov, won, snd, to_next, nb, nproc,
                                     epoch, b0, gprev, gnext, G, QC, head, tail, ovn, claims,
-                                    cprev, cnext, credit, st);
-            }
-            if (G > 1u && tid == 0) {
-                if (pend_ok && !pend_new) {
-                    sh[3] = (uint32_t)pend_tail;                  // read during the last step
-                    sh[7] = (uint32_t)(pend_tail >> 32);
-                    pend_ok = false;
-                }
-                pend_new = false;
+                                    cprev, cnext, credit, tr, st);
             }
             __syncthreads();
             if (WOLFF_STATS && tid == 0) {
