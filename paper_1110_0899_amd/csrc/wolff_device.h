@@ -39,6 +39,40 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
     return U4{c0, c1, c2, c3};
 }
 
+// K blocks that share words 1..3 and the key (the bond blocks a site needs),
+// with their rounds interleaved so that the K dependent chains overlap.
+template <int K>
+__device__ __forceinline__ void philox_multi(const uint32_t (&c0)[K], uint32_t c1, uint32_t c2,
+                                             uint32_t c3, uint32_t k0, uint32_t k1, U4 (&out)[K])
+{
+    uint32_t x0[K], x1[K], x2[K], x3[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        x0[i] = c0[i];
+        x1[i] = c1;
+        x2[i] = c2;
+        x3[i] = c3;
+    }
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const uint64_t p0 = (uint64_t)0xD2511F53u * x0[i];
+            const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2[i];
+            const uint32_t n0 = (uint32_t)(p1 >> 32) ^ x1[i] ^ k0;
+            const uint32_t n2 = (uint32_t)(p0 >> 32) ^ x3[i] ^ k1;
+            x1[i] = (uint32_t)p1;
+            x3[i] = (uint32_t)p0;
+            x0[i] = n0;
+            x2[i] = n2;
+        }
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) out[i] = U4{x0[i], x1[i], x2[i], x3[i]};
+}
+
 // Random stream domains (word 3 of the counter).
 constexpr uint32_t DOMAIN_BOND = 0u;
 constexpr uint32_t DOMAIN_SEED = 1u;
