@@ -28,16 +28,17 @@
 // with a plain store; entries carry the update index, so a receiver that
 // reads an end before the entries below it simply waits for their tags.
 // A device-scope counter P = (t + 1) << 32 | outstanding units decides when
-// the cluster is complete.  The units are claimed sites not yet expanded,
-// messages not yet consumed, and credit: before a step that could send more
-// messages than its workgroup's remaining credit, the workgroup adds a block
-// of credit to P (the addition issued at the step's start and waited for
-// before the step's messages are written, so its latency hides behind the
-// expansion); a message spends one unit of credit, the receiver removes it
-// when it consumes the message, and a workgroup that runs out of work hands
-// its unspent credit back.  Every other change (sites claimed minus sites
-// expanded) is added once per step without waiting, so P never reaches 0
-// while work or a message is left.  After P reaches
+// the cluster is complete.  The units are one per busy workgroup (a
+// workgroup with sites to expand), one per message not yet consumed, and
+// credit: before a step that could send more messages than its workgroup's
+// remaining credit, the workgroup adds a block of credit to P (the addition
+// issued at the step's start and waited for before the step's messages are
+// written, so its latency hides behind the expansion); a message spends one
+// unit of credit, and the receiver removes it when it consumes the message,
+// in the same addition that takes the receiver's busy unit if the message
+// gave it sites.  A workgroup that runs out of work hands back its busy unit
+// and its unspent credit.  So P never reaches 0 while work or a message is
+// left, and a busy workgroup's steps leave P alone.  After P reaches
 // 0 the team counts the bond sum (every slab its rows plus the rows it
 // shares with the next slab, whose first row each slab publishes) and its
 // negative spins, and the last workgroup at the update's grid barrier writes
@@ -306,13 +307,14 @@ struct TailRead {
 // Second half of a growth step, for NS neighbour slots per lane: compaction
 // of the claimed sites and of the messages (to the previous / next slab),
 // publication of the ring ends read a step earlier, the messages (paid from
-// the credit), the step's net change of P in sites, and the claimed sites
-// appended to the ring or the overflow stack.
+// the credit), and the claimed sites appended to the ring or the overflow
+// stack.  A busy workgroup's own sites are not counted in P (its one busy
+// unit stands for all of them), so a step changes P only through credit.
 template <int WG, int NS>
-__device__ __forceinline__ void lds_publish(const LdsArgs& a, LdsCtl* ctl, uint32_t* q, uint32_t* wave_cnt,
+__device__ __forceinline__ void lds_publish(const LdsArgs& a, uint32_t* q, uint32_t* wave_cnt,
                                             uint32_t* wave_snd, uint32_t* sh, gword* ov, const bool won[NS],
                                             const bool snd[NS], const bool to_next[NS],
-                                            const uint32_t nb[NS], uint32_t nproc,
+                                            const uint32_t nb[NS],
                                             unsigned long long epoch, uint32_t b0, uint32_t gprev,
                                             uint32_t gnext, uint32_t G, uint32_t QC, uint32_t& head,
                                             uint32_t& tail, uint32_t& ovn, uint32_t& claims,
@@ -398,14 +400,7 @@ __device__ __forceinline__ void lds_publish(const LdsArgs& a, LdsCtl* ctl, uint3
                 st.add(WOLFF_STAT_STEPS_SEND, 1u);
             }
         }
-        if (tid == 0) {
-            credit -= ptot + ntot;
-            const long long delta = (long long)total - (long long)nproc;
-            if (delta != 0) {
-                __hip_atomic_fetch_add(&ctl->P, (unsigned long long)delta, __ATOMIC_RELAXED, SCOPE_AGENT);
-                st.add(WOLFF_STAT_ATOMIC_BYTES, 8u);
-            }
-        }
+        if (tid == 0) credit -= ptot + ntot;
     }
     // append the claimed sites to the ring (or the overflow stack); the
     // counters move by selects, not through a reference chosen by branch
@@ -562,6 +557,7 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
         uint32_t claims = 0u, nstep = 0u;
         TailRead tr{0u, false, false};
         credit = 0u;
+        bool busy = false;                                        // thread 0: one unit of P held
         if (tid == 0 && g == 0u) st.add(WOLFF_STAT_UPDATES, 1u);
         if (g == owner) {
             if (tid == 0) {
@@ -573,6 +569,7 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
                 sh[2] = 1u;                                       // s0 known
                 if (G > 1u)
                     __hip_atomic_store(&ctl->P, epoch | 1ull, __ATOMIC_RELAXED, SCOPE_AGENT);
+                busy = true;                                      // the unit just stored
             }
             tail = 1u;
             claims = 1u;
@@ -605,11 +602,13 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
                 if (avail == 0u) {
                     if (tid == 0) {
                         const uint64_t c_idle = WOLFF_STATS ? clock64() : 0u;
-                        if (credit) {                             // out of work: hand the credit back
-                            __hip_atomic_fetch_add(&ctl->P, (unsigned long long)(0ll - (long long)credit),
+                        if (busy || credit) {                     // out of work: hand back the busy unit and the credit
+                            const long long back = (long long)credit + (busy ? 1ll : 0ll);
+                            __hip_atomic_fetch_add(&ctl->P, (unsigned long long)(0ll - back),
                                                    __ATOMIC_RELAXED, SCOPE_AGENT);
                             st.add(WOLFF_STAT_ATOMIC_BYTES, 8u);
                             credit = 0u;
+                            busy = false;
                         }
                         const uint64_t ih = ((uint64_t)ihead1 << 32) | ihead0;
                         uint64_t it = ld_tails(a.inbox_tail, g);
@@ -715,7 +714,11 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
                 ihead1 += m1;
                 if (tid == 0) {
                     sh[2] = 1u;
-                    const long long delta = (long long)total - (long long)m;
+                    // the consumed messages leave P in the same addition that
+                    // takes the busy unit if the workgroup now has sites
+                    const bool wake = !busy && total > 0u;
+                    const long long delta = (wake ? 1ll : 0ll) - (long long)m;
+                    busy = busy || wake;
                     if (delta != 0) {
                         __hip_atomic_fetch_add(&ctl->P, (unsigned long long)delta, __ATOMIC_RELAXED, SCOPE_AGENT);
                         st.add(WOLFF_STAT_ATOMIC_BYTES, 8u);
@@ -784,7 +787,7 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
                 if (tid == 0) st.add(WOLFF_STAT_STEPS_NARROW, 1u);
                 if (WOLFF_STATS && tid == 0) c_pub = clock64();
                 if (refill) credit_wait(c_pub, st);
-                lds_publish<WG, 1>(a, ctl, q, wave_cnt, wave_snd, sh, ov, won, snd, to_next, nb1, nproc,
+                lds_publish<WG, 1>(a, q, wave_cnt, wave_snd, sh, ov, won, snd, to_next, nb1,
                                    epoch, b0, gprev, gnext, G, QC, head, tail, ovn, claims,
                                    cprev, cnext, credit, tr, st);
             } else {
@@ -851,7 +854,7 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
                 }
                 if (WOLFF_STATS && tid == 0) c_pub = clock64();
                 if (refill) credit_wait(c_pub, st);
-                lds_publish<WG, D2>(a, ctl, q, wave_cnt, wave_snd, sh, ov, won, snd, to_next, nb, nproc,
+                lds_publish<WG, D2>(a, q, wave_cnt, wave_snd, sh, ov, won, snd, to_next, nb,
                                     epoch, b0, gprev, gnext, G, QC, head, tail, ovn, claims,
                                     cprev, cnext, credit, tr, st);
             }
