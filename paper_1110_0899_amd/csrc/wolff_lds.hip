@@ -444,7 +444,7 @@ struct LdsShm {
     uint32_t wave_cnt[NW];
     uint32_t wave_snd[2 * NW];
     uint64_t red[2 * NW];
-    uint32_t sh[12];
+    uint32_t sh[16];
 };
 
 // All updates of one lattice (up to max_updates, or until the wall-clock
@@ -452,14 +452,16 @@ struct LdsShm {
 // other G - 1 workgroups of the launch.  MULTI: the lattice spans several
 // slabs (messages, P, grid barriers through a.ctl); otherwise this one
 // workgroup holds it all, every team-only branch compiles away and a.ctl
-// is not used.
-template <int WG, int DIM, bool MULTI>
+// is not used.  TINY: frontiers one wave holds run level after level in
+// that wave alone (see the step).
+template <int WG, int DIM, bool MULTI, bool TINY>
 __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates, uint64_t budget,
                                          uint64_t t_start, uint32_t* lds, LdsShm<WG / WAVE>& shm)
 {
     constexpr int NW = WG / WAVE;
     constexpr int D2 = 2 * DIM;
     constexpr uint32_t BOND_SITES = (uint32_t)(WG / D2);    // sites of a one-lane-per-bond step
+    constexpr uint32_t TINY_SITES = (uint32_t)(WAVE / D2);  // sites one wave holds, one lane per bond
     uint32_t* wave_cnt = shm.wave_cnt;
     uint32_t* wave_snd = shm.wave_snd;
     uint64_t* red = shm.red;
@@ -752,7 +754,110 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
             uint64_t c_pub = c_step;
             if (tid == 0) st.add(WOLFF_STAT_STEPS, 1u);
             if (look && tid == 0) st.add(WOLFF_STAT_READ_BYTES, 8u);
-            if (avail <= BOND_SITES) {
+            if (TINY && avail <= TINY_SITES && ovn == 0u) {
+                // ---- a frontier that one wave holds, one lane per bond: wave 0
+                // runs level after level alone, with no workgroup barrier, while
+                // the frontier stays that small (split lattice: at most 16
+                // levels, so that the ring ends are still read); the other waves
+                // wait at the barrier below.  One wave's LDS accesses are
+                // performed in order, so a level sees the bits and ring entries
+                // the previous one wrote.
+                if (wv == 0u) {
+                    uint32_t av = avail, lv = 0u;
+                    while (true) {
+                        const uint32_t si = lane / (uint32_t)D2;
+                        const uint32_t m = lane - si * (uint32_t)D2;
+                        const bool active = si < av;
+                        const uint32_t j = active ? q[(head + si) & a.qmask] : 0u;
+                        head += av;
+                        if (G > 1u && lv > 0u && tid == 0 && credit < 2u * av) {
+                            __hip_atomic_fetch_add(&ctl->P, (unsigned long long)credit_block<WG>(),
+                                                   __ATOMIC_RELAXED, SCOPE_AGENT);
+                            credit += credit_block<WG>();
+                            refill = true;
+                            st.add(WOLFF_STAT_ATOMIC_BYTES, 8u);
+                        }
+                        uint32_t nr, nc;
+                        lds_neighbour<DIM>(lg, j, m, nr, nc);
+                        const uint32_t nbk = nc + nr * L;
+                        const bool local = !MULTI || (nr >= r0 && nr < r0 + nrows);
+                        const uint32_t ba = local ? slab_bit(lg, nc, nr, r0) : 0u;
+                        const bool elig = active && (!local || bit_of(bits, ba) == b0);
+                        uint32_t rr = 0xFFFFFFFFu;
+                        if (active) {
+                            const U4 w4 = philox((m & 1u) ? nbk : j, t, s, DOMAIN_BOND, k0, k1);
+                            const uint32_t mu = m >> 1;
+                            rr = (mu == 0u) ? w4.x : (mu == 1u) ? w4.y : w4.z;
+                        }
+                        const bool act = elig && rr < thr;
+                        const bool won = act && local && claim_bit(bits, ba, b0);
+                        const bool snd = act && !local;
+                        const bool nxt = (m & 1u) == 0u;
+                        st.add(WOLFF_STAT_SITES, (active && m == 0u) ? 1u : 0u);
+                        st.add(WOLFF_STAT_NEIGHBOUR_READS, (active && local) ? 1u : 0u);
+                        st.add(WOLFF_STAT_PHILOX, active ? 1u : 0u);
+                        st.add(WOLFF_STAT_CLAIMS, (act && local) ? 1u : 0u);
+                        if (G > 1u) {
+                            const uint64_t mp = __ballot(snd && !nxt), mn = __ballot(snd && nxt);
+                            const uint32_t ptot = (uint32_t)__popcll(mp), ntot = (uint32_t)__popcll(mn);
+                            if (ptot + ntot > 0u) {
+                                if (refill) {
+                                    credit_wait(c_pub, st);           // the credit is in P
+                                    refill = false;
+                                }
+                                if (snd) {
+                                    const unsigned long long word = epoch | (b0 ? MSG_S0_NEG : 0u);
+                                    const uint32_t QI = a.imask + 1u;
+                                    const size_t ring = nxt ? 2u * (size_t)gnext : 2u * (size_t)gprev + 1u;
+                                    const uint32_t slot = nxt ? cnext + lane_prefix(mn) : cprev + lane_prefix(mp);
+                                    __hip_atomic_store(&a.inbox[ring * QI + (slot & a.imask)], word | nbk,
+                                                       __ATOMIC_RELAXED, SCOPE_AGENT);
+                                    st.add(WOLFF_STAT_WRITE_BYTES, 8u);
+                                    st.add(WOLFF_STAT_MESSAGES, 1u);
+                                }
+                                cprev += ptot;
+                                cnext += ntot;
+                                if (tid == 0) {
+                                    if (ptot) __hip_atomic_store(&a.inbox_tail[2u * gprev + 1u], cprev, __ATOMIC_RELAXED, SCOPE_AGENT);
+                                    if (ntot) __hip_atomic_store(&a.inbox_tail[2u * gnext], cnext, __ATOMIC_RELAXED, SCOPE_AGENT);
+                                    credit -= ptot + ntot;
+                                    st.add(WOLFF_STAT_WRITE_BYTES, (ptot ? 4u : 0u) + (ntot ? 4u : 0u));
+                                    st.add(WOLFF_STAT_STEPS_SEND, 1u);
+                                }
+                            }
+                        }
+                        // the claimed sites to the ring (it is empty: all av were taken)
+                        const uint64_t wm = __ballot(won);
+                        const uint32_t total = (uint32_t)__popcll(wm);
+                        if (won) q[(tail + lane_prefix(wm)) & a.qmask] = nbk;
+                        tail += total;
+                        claims += total;
+                        ++lv;
+                        if (tid == 0) st.add(WOLFF_STAT_STEPS_NARROW, 1u);
+                        av = total;
+                        if (av == 0u || av > TINY_SITES || (G > 1u && lv >= 16u)) break;
+                        if (tid == 0) st.add(WOLFF_STAT_STEPS, 1u);
+                    }
+                    if (tid == 0) {
+                        if (refill) credit_wait(c_pub, st);       // credit a later step may spend
+                        sh[8] = head;
+                        sh[9] = tail;
+                        sh[11] = claims;
+                        sh[12] = cprev;
+                        sh[13] = cnext;
+                        sh[14] = lv;
+                        tr.fresh = false;                         // published by a later step
+                    }
+                }
+                if (WOLFF_STATS && tid == 0) c_pub = clock64();
+                __syncthreads();
+                head = sh[8];
+                tail = sh[9];
+                claims = sh[11];
+                cprev = sh[12];
+                cnext = sh[13];
+                nstep += sh[14] - 1u;
+            } else if (avail <= BOND_SITES) {
                 const uint32_t si = tid / (uint32_t)D2;
                 const uint32_t m = tid - si * (uint32_t)D2;
                 const uint32_t nproc = min(avail, BOND_SITES);
@@ -1011,13 +1116,20 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
     }
 }
 
-// One lattice, on G workgroups (MULTI) or one.
+// One lattice, on G workgroups (MULTI) or one.  Tiny frontiers run in one
+// wave (TINY) on split lattices and on one-slab workgroups of up to 256
+// threads, where the library puts lattices below 2^18 sites: measured on
+// MI355X, 2D L = 32 (C1) 29.7 -> 24.0 us per update, 2D L = 4096 at T_c
+// 7.55 -> 7.32 ms, 3D L = 256 0.294 -> 0.256 ms; on one-slab 512-thread
+// workgroups (wide frontiers, 2D L = 512 and 1024) the wave path was 2-3 %
+// slower, and in the batched form a C4 mix ran 14 % longer, so those leave
+// it out.
 template <int WG, int DIM, bool MULTI>
 __global__ __launch_bounds__(WG) void lds_kernel(LdsArgs a, uint32_t max_updates)
 {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ LdsShm<WG / WAVE> shm;
-    lds_body<WG, DIM, MULTI>(a, max_updates, 0u, 0u, lds, shm);
+    lds_body<WG, DIM, MULTI, MULTI || WG <= 256>(a, max_updates, 0u, 0u, lds, shm);
 }
 
 // Batched form of the LDS path for lattices that fit one workgroup: each
@@ -1050,9 +1162,9 @@ __global__ __launch_bounds__(WG) void lds_batch_kernel(Rep* reps, const LdsGeo* 
         a.qmask = qmask;
         a.lg = geos[r];
         if (DIMS == 2 || (DIMS == 0 && reps[r].dim == 2))
-            lds_body<WG, 2, false>(a, max_updates, budget, t_start, lds, shm);
+            lds_body<WG, 2, false, false>(a, max_updates, budget, t_start, lds, shm);
         else
-            lds_body<WG, 3, false>(a, max_updates, budget, t_start, lds, shm);
+            lds_body<WG, 3, false, false>(a, max_updates, budget, t_start, lds, shm);
         if (threadIdx.x == 0) {
             const bool spent = budget != 0u && wall_clock64() - t_start >= budget;
             idx_sh = spent ? n_reps : gridDim.x + atomicAdd(next, 1u);
