@@ -264,8 +264,8 @@ int wolff_set_stream(wolff_sim *s, void *hip_stream);
  * frontier queue, one launch for many updates); WOLFF_PATH_TEAM runs each
  * update on `workgroups` cooperating workgroups (0 = library default) that
  * share an atomic-counter frontier.  WOLFF_PATH_AUTO takes the LDS path
- * for Ising lattices it holds in one workgroup, and for those of at least
- * 2^22 sites it holds at all; otherwise the path with the lower estimated
+ * for Ising lattices it holds in one or two workgroups, and for those of at
+ * least 2^22 sites it holds at all; otherwise the path with the lower estimated
  * cost per update of the other two, from the mean cluster size of the
  * latest records (at most 256) returned by wolff_observables, the lattice
  * size and the measurement mode (both costs grow with the cluster's

@@ -473,18 +473,18 @@ static bool lds_fits(const wolff_sim* s)
            (int)p.lg.G <= device_cus();
 }
 
-// Ising lattices the LDS path holds in one workgroup, or in several when
-// the lattice has at least 2^22 sites: there it was the fastest path at
-// every measured size and temperature window on MI355X (square lattices
-// L = 32 ... 4096 and simple-cubic L = 32, 64, 256 at their critical
-// points, 1.2x to 1.5x the best of the other two).  A lattice split over a
-// few slabs (simple-cubic L = 128 on two) was slower than one workgroup,
-// so smaller split lattices stay with the cost model below.
+// Ising lattices the LDS path holds in one or two workgroups, or in more
+// when the lattice has at least 2^22 sites: there it was the fastest path
+// at every measured size and temperature window on MI355X (square lattices
+// L = 32 ... 4096, simple-cubic L = 32 ... 256 at their critical points;
+// simple-cubic L = 128 on two slabs 0.275 against 0.294 ms per update on
+// one workgroup).  Lattices below 2^22 sites split into more slabs (a
+// lowered slab size) stay with the cost model below.
 static bool lds_preferred(const wolff_sim* s)
 {
     LdsPlan p;
     if (!lds_fits(s) || !lds_plan(s->dim, (uint32_t)s->L, s->lds_slab_bits, &p)) return false;
-    return p.lg.G == 1u || s->N >= (1ull << 22);
+    return p.lg.G <= 2u || s->N >= (1ull << 22);
 }
 
 static int resolved_path(const wolff_sim* s)
