@@ -837,6 +837,10 @@ __device__ __forceinline__ void lds_body(const LdsArgs& a, uint32_t max_updates,
                         av = total;
                         if (av == 0u || av > TINY_SITES || (G > 1u && lv >= 16u)) break;
                         if (tid == 0) st.add(WOLFF_STAT_STEPS, 1u);
+                        // the next level's lanes read what other lanes of the
+                        // wave wrote: order the wave's LDS accesses across levels
+                        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
                     }
                     if (tid == 0) {
                         if (refill) credit_wait(c_pub, st);       // credit a later step may spend
