@@ -97,3 +97,23 @@ def test_kernel_stats_reader(tmp_path):
     assert "    cmd --x" in text and "a note" in text
     assert "| `void wolff::team_kernel<256, 2>` | 4 | 4.0 | 1.000 | 90.00 |" in text
     assert text.strip().endswith(profiling.kernel_source_sha())
+
+
+def test_pmc_table_sums_the_last_dispatches(tmp_path):
+    # one --pmc run with two counters: the table averages each counter over
+    # the kernel's last n dispatches (sorted by id) and divides the sum by
+    # the added spins; other kernels' rows are left out
+    k = "void wolff::lds_kernel<512, 2, true>(wolff::LdsArgs, unsigned int)"
+    d = write_counters(str(tmp_path / "sq"), [
+        (4, k, "SQ_INSTS_VALU", 40.0), (2, k, "SQ_INSTS_VALU", 20.0), (6, k, "SQ_INSTS_VALU", 60.0),
+        (2, k, "SQ_INSTS_LDS", 2.0), (4, k, "SQ_INSTS_LDS", 4.0), (6, k, "SQ_INSTS_LDS", 6.0),
+        (5, "wolff::init_kernel", "SQ_INSTS_VALU", 1e9)])
+    out = str(tmp_path / "sq.md")
+    a = argparse.Namespace(kernel="lds_kernel", dir=d, out=out, command="cmd", last=2, added=10.0,
+                           note="")
+    profiling.pmc_table(a)
+    text = open(out).read()
+    assert "`void wolff::lds_kernel<512, 2, true>`" in text
+    assert "| `SQ_INSTS_VALU` | 50 | 10 |" in text          # (40 + 60) / 2, (40 + 60) / 10
+    assert "| `SQ_INSTS_LDS` | 5 | 1 |" in text
+    assert profiling.kernel_source_sha() in text
