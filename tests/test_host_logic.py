@@ -100,3 +100,18 @@ def test_bench_refuses_several_gpus():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
+
+
+def test_stat_names_follow_the_header():
+    # the binding names the counting build's counters in the header's order
+    import re
+    from paper_1110_0899_amd import binding
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    text = open(os.path.join(root, "include", "wolff.h")).read()
+    defs = {m.group(1): int(m.group(2))
+            for m in re.finditer(r"#define WOLFF_STAT_([A-Z_]+)\s+(\d+)", text)}
+    count = defs.pop("COUNT")
+    assert sorted(defs.values()) == list(range(count))
+    assert binding.STAT_COUNT == count == len(binding.STAT_NAMES)
+    for name, idx in defs.items():
+        assert binding.STAT_NAMES[idx] == name.lower(), (name, idx)
