@@ -385,6 +385,27 @@ def test_auto_path_picks_one_workgroup_for_mid_size_clusters():
     assert (np.concatenate(parts) == ref).all()
 
 
+def test_auto_takes_two_slab_lattices_to_lds():
+    # simple-cubic L = 128 (2^21 sites) needs two LDS slabs; AUTO takes the
+    # LDS path for it, and its records and spins follow the oracle from the
+    # random start and from the ordered start (lattice-scale clusters that
+    # cross between the two slabs at every update)
+    dim, L, T, seed = 3, 128, T3, 41
+    thr = oracle.threshold(1.0, T)
+    print("case auto two slabs 3D L=128", flush=True)
+    for start, n in (("random", 20), ("ordered", 8)):
+        S0 = oracle.init_spins(dim, L, seed) if start == "random" else np.ones(L ** dim, dtype=np.int8)
+        ref = oracle.run(dim, L, thr, seed, 0, n, S0)
+        with binding.Simulation(dim, L, 1.0, T, seed) as sim:
+            if start == "ordered":
+                sim.set_spins(np.ones(L ** dim, dtype=np.int8), 0)
+            assert sim.info().path == binding.PATH_LDS
+            sim.run(n)
+            got = as_array(sim.observables())
+            assert (sim.spins() == S0).all(), start
+        assert (got == ref).all(), start
+
+
 @pytest.mark.parametrize("wg,q", [(64, 64), (128, 128), (256, 2048), (512, 4096), (1024, 1024),
                                   (1024, 8192)])
 def test_tile_sizes_single_and_batch(wg, q):
