@@ -295,8 +295,8 @@ int wolff_set_lds_slab(wolff_sim *s, uint32_t slab_bits);
 
 /* LDS-resident path: threads per workgroup (the paper's block size,
  * Section 4), 64, 128, 256, 512 or 1024; 0 restores the default (512 for
- * a lattice on several slabs; on one slab 128 up to 2048 spins, 256 up to
- * 16384, 512 above).  WOLFF_EINVAL otherwise. */
+ * a lattice on several slabs; on one slab 128 for square lattices up to
+ * 1024 spins, 256 up to 16384, 512 above).  WOLFF_EINVAL otherwise. */
 int wolff_set_lds_tiles(wolff_sim *s, int wg);
 
 /* Team path: replay a captured HIP graph of `chunk` updates (step (v) of

@@ -430,12 +430,13 @@ static bool lds_plan(int dim, uint32_t L, uint32_t slab_bits, LdsPlan* out)
     const uint64_t N = lg.N;
     // measured on MI355X at the critical points: 512 threads per slab for a
     // split lattice (2D L = 4096: 10.0 ms per update against 11.2 with 256,
-    // 10.5 with 1024; 3D L = 256: 0.34 ms against 0.41); one slab: 128 up
-    // to 2048 spins (2D L = 32: 30 us against 35 with 64), 256 up to 16384
-    // (2D L = 64: 55 us against 61 with 128, 66 with 512), 512 above (2D
+    // 10.5 with 1024; 3D L = 256: 0.34 ms against 0.41); one slab: 128 for
+    // square lattices up to 1024 spins (2D L = 32: 24.4 us, 24.7 with 256,
+    // 29 with 64), 256 up to 16384 (2D L = 45, 64: 36, 55 us against 38, 61
+    // with 128; 3D L = 12, 16: 16, 22 us against 18, 27), 512 above (2D
     // L = 181, 256, 512, 1024: 0.19, 0.27, 0.64, 1.56 ms against 0.21,
     // 0.30, 0.73, 1.79 with 256; 3D L = 32, 40: 47, 65 us against 51, 75)
-    p.wg = lg.G > 1u ? 512 : N <= 2048 ? 128 : N <= 16384 ? 256 : 512;
+    p.wg = lg.G > 1u ? 512 : (dim == 2 && N <= 1024) ? 128 : N <= 16384 ? 256 : 512;
     // a message ring carries the bonds across one slab boundary in one
     // direction, each at most once per update: L^(d-1) entries
     uint32_t cap = 64u;
