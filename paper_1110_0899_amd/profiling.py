@@ -40,13 +40,41 @@ DEVICE_SOURCES = ("wolff_device.h", "wolff_kernels.h", "wolff_kernels.hip", "wol
                   "../../include/wolff.h")
 
 
+def code_tokens(text: str) -> str:
+    """C/C++ source with its comments removed and each run of whitespace
+    made one space (string and character literals kept as written), so that
+    a change to documentation alone leaves the hash of the code as it was."""
+    out = []
+    i, n = 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_sha() -> str:
-    """Hash of the device sources (the one bench.py checks counter files against)."""
+    """Hash of the device code (the one bench.py checks counter files
+    against): the sources' tokens, comments and layout left out."""
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "csrc")
     for name in DEVICE_SOURCES:
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + f.read())
+        with open(os.path.join(csrc, name), encoding="utf-8") as f:
+            h.update(name.encode() + b"\0" + code_tokens(f.read()).encode())
     return h.hexdigest()[:16]
 
 

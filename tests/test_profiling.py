@@ -117,3 +117,15 @@ def test_pmc_table_sums_the_last_dispatches(tmp_path):
     assert "| `SQ_INSTS_VALU` | 50 | 10 |" in text          # (40 + 60) / 2, (40 + 60) / 10
     assert "| `SQ_INSTS_LDS` | 5 | 1 |" in text
     assert profiling.kernel_source_sha() in text
+
+
+def test_source_hash_ignores_comments_only():
+    # a documentation edit keeps the hash, a change to a token does not
+    src = 'int f(int a) { // add one\n  return a + 1; /* sum */ }\nconst char* s = "x // y";\n'
+    doc = 'int f(int a)\n{\n    /* adds one */ return a + 1;\n}\nconst char* s = "x // y"; // text\n'
+    code = 'int f(int a) { return a + 2; }\nconst char* s = "x // y";\n'
+    assert profiling.code_tokens(src) == profiling.code_tokens(doc)
+    assert profiling.code_tokens(src) != profiling.code_tokens(code)
+    assert '"x // y"' in profiling.code_tokens(src)
+    assert profiling.code_tokens("a /* b */ c") == "a c"
+    assert profiling.code_tokens("char c = '\\'';") == "char c = '\\'';"
