@@ -785,9 +785,14 @@ static int reserve_records(wolff_sim* s, uint64_t n)
     wolff_record* nrec = nullptr;
     HIP_TRY(hipMalloc(&nrec, cap * sizeof(wolff_record)));
     const uint64_t live = s->rec_written - s->rec_read;
-    if (live)
-        HIP_TRY(copy_wait(s->stream, nrec, s->d_rec + s->rec_read, live * sizeof(wolff_record),
-                          hipMemcpyDeviceToDevice));
+    if (live) {
+        const hipError_t e = copy_wait(s->stream, nrec, s->d_rec + s->rec_read,
+                                       live * sizeof(wolff_record), hipMemcpyDeviceToDevice);
+        if (e != hipSuccess) {   // the old buffer and its records stay in place
+            (void)hipFree(nrec);
+            return fail(WOLFF_EDEVICE, std::string("record buffer copy: ") + hipGetErrorString(e));
+        }
+    }
     HIP_TRY(hipFree(s->d_rec));
     s->d_rec = nrec;
     s->rec_cap = cap;
@@ -805,8 +810,14 @@ static int ensure_team_queue(wolff_sim* s)
 {
     if (s->gq) return WOLFF_OK;
     HIP_TRY(hipStreamSynchronize(s->stream));
-    HIP_TRY(hipMalloc(&s->gq, s->N * sizeof(unsigned long long)));
-    HIP_TRY(hipMemsetAsync(s->gq, 0, s->N * sizeof(unsigned long long), s->stream));
+    unsigned long long* q = nullptr;
+    HIP_TRY(hipMalloc(&q, s->N * sizeof(unsigned long long)));
+    const hipError_t e = hipMemsetAsync(q, 0, s->N * sizeof(unsigned long long), s->stream);
+    if (e != hipSuccess) {       // kept only once zeroed: a later call must not find it half set up
+        (void)hipFree(q);
+        return fail(WOLFF_EDEVICE, std::string("team queue fill: ") + hipGetErrorString(e));
+    }
+    s->gq = q;
     return WOLFF_OK;
 }
 
@@ -834,9 +845,8 @@ static int lds_reset(wolff_sim* s)
     return WOLFF_OK;
 }
 
-static int ensure_lds(wolff_sim* s, const LdsPlan& p)
+static int alloc_lds(wolff_sim* s, const LdsPlan& p)
 {
-    if (s->lctl) return WOLFF_OK;
     const uint32_t G = p.lg.G;
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->lbytes_inbox = 2u * (size_t)G * (p.imask + 1u) * sizeof(unsigned long long);
@@ -849,6 +859,16 @@ static int ensure_lds(wolff_sim* s, const LdsPlan& p)
     HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(lds_fn(p.wg, s->dim, p.lg.G)),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes));
     return lds_reset(s);
+}
+
+// The buffers are kept only when all of them were set up: a later call
+// takes a non-null control block as "ready".
+static int ensure_lds(wolff_sim* s, const LdsPlan& p)
+{
+    if (s->lctl) return WOLFF_OK;
+    const int rc = alloc_lds(s, p);
+    if (rc) free_lds(s);
+    return rc;
 }
 
 static int run_lds(wolff_sim* s, uint64_t n)
@@ -966,9 +986,11 @@ static int ensure_team_graph(wolff_sim* s)
         return rc;
     }
     HIP_TRY(e);
-    const hipError_t ei = hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0);
+    hipGraphExec_t x = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     HIP_TRY(ei);
+    s->graph = x;
     s->graph_stream = s->stream;
     for (int i = 0; i < 3; ++i) s->graph_key[i] = key[i];
     return WOLFF_OK;
