@@ -43,8 +43,12 @@ def test_binding_covers_every_declared_symbol():
 
 
 def test_error_strings(lib):
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (binding.OK, binding.EINVAL, binding.ENOMEM, binding.EDEVICE, binding.ERANGE,
+                 binding.ESTATE, binding.EABORTED):
         assert lib.wolff_strerror(code)
+    # every code has its own text
+    texts = {lib.wolff_strerror(c) for c in range(-6, 1)}
+    assert len(texts) == 7
 
 
 @pytest.mark.parametrize("dim,L,J,T", [(1, 8, 1.0, 2.0), (4, 8, 1.0, 2.0), (2, 1, 1.0, 2.0),
@@ -78,3 +82,32 @@ def test_noalloc_rejects_sizes_beyond_its_fixed_array(lib):
     for dim, L in ((2, 1025), (3, 102)):
         assert lib.wolff_run_noalloc(dim, L, 1.0, 2.0, 1, None, 0, 0, 1, 1, None, None) == binding.EINVAL
         assert b"scratch" in lib.wolff_last_error()
+
+
+def job(**kw):
+    j = binding.JobDesc(dim=2, L=16, J=1.0, T=2.269, seed=1, n_updates=10, start=0, flags=0, q=0)
+    for k, v in kw.items():
+        setattr(j, k, v)
+    return j
+
+
+@pytest.mark.parametrize("bad,code", [(dict(start=2), binding.EINVAL), (dict(start=-2), binding.EINVAL),
+                                      (dict(flags=2), binding.EINVAL), (dict(q=1), binding.EINVAL),
+                                      (dict(q=128), binding.EINVAL), (dict(dim=4), binding.EINVAL),
+                                      (dict(L=1), binding.EINVAL), (dict(T=0.0), binding.EINVAL),
+                                      (dict(n_updates=1 << 32), binding.ERANGE)])
+def test_batch_create_rejects_bad_jobs(lib, bad, code):
+    # every job is checked before any device call; the message names the job
+    jobs = (binding.JobDesc * 2)(job(), job(**bad))
+    h = ctypes.c_void_p()
+    assert lib.wolff_batch_create(jobs, 2, ctypes.byref(h)) == code
+    assert not h.value
+    assert lib.wolff_last_error().startswith(b"job 1")
+
+
+def test_batch_create_rejects_an_empty_list(lib):
+    h = ctypes.c_void_p()
+    jobs = (binding.JobDesc * 1)(job())
+    assert lib.wolff_batch_create(jobs, 0, ctypes.byref(h)) == binding.EINVAL
+    assert lib.wolff_batch_create(jobs, -1, ctypes.byref(h)) == binding.EINVAL
+    assert lib.wolff_batch_create(jobs, 1, None) == binding.EINVAL
