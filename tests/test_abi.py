@@ -111,3 +111,37 @@ def test_batch_create_rejects_an_empty_list(lib):
     assert lib.wolff_batch_create(jobs, 0, ctypes.byref(h)) == binding.EINVAL
     assert lib.wolff_batch_create(jobs, -1, ctypes.byref(h)) == binding.EINVAL
     assert lib.wolff_batch_create(jobs, 1, None) == binding.EINVAL
+
+
+HANDLE_DESTROY = ("wolff_destroy", "wolff_batch_destroy", "wolff_server_destroy")
+
+
+def null_args(argtypes):
+    # a NULL handle first, then zeros and NULL pointers
+    out = []
+    for t in argtypes:
+        if t in (ctypes.c_double,):
+            out.append(0.0)
+        elif t in (ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64):
+            out.append(0)
+        else:
+            out.append(None)
+    return out
+
+
+def test_every_handle_call_rejects_a_null_handle(lib):
+    # every entry point that takes a sim, batch or server handle checks it
+    # first; destroying NULL is a no-op
+    header = open(HEADER).read()
+    takes_handle = set(re.findall(r"\b(wolff_\w+)\s*\(\s*(?:const\s+)?wolff_(?:sim|batch|server)\s*\*",
+                                  re.sub(r"/\*.*?\*/", "", header, flags=re.S)))
+    assert len(takes_handle) > 30
+    for name in sorted(takes_handle):
+        _, argtypes = binding.SIGNATURES[name]
+        rc = getattr(lib, name)(*null_args(argtypes))
+        assert rc == (binding.OK if name in HANDLE_DESTROY else binding.EINVAL), name
+
+
+def test_server_rejects_bad_arguments_before_the_device(lib):
+    assert lib.wolff_server_create(0, -1, ctypes.byref(ctypes.c_void_p())) == binding.EINVAL
+    assert lib.wolff_server_create(0, 4, None) == binding.EINVAL
