@@ -184,7 +184,7 @@ def test_special_cases():
 
 
 @pytest.mark.parametrize("lds", [True, False])
-def test_batch_matches_alone(lds):
+def test_batch_matches_oracle(lds):
     # lds: these lattices run on the batched LDS path, in both LDS-size
     # classes (square L = 600 and cubic L = 70 need more than 8 KiB
     # of LDS); off: all on the one-workgroup kernel
